@@ -60,6 +60,7 @@ def lib():
         L.ora_grad_A.argtypes = [ctypes.c_int, _i64p, ctypes.c_int, _vp, _vp, _vp]
         L.ora_separation.argtypes = [ctypes.c_int, _i64p, _vp]
         L.ora_separation.restype = ctypes.c_double
+        L.ora_num_threads.restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -261,6 +262,29 @@ def apply_at(n, A_list, fetch, indices):
                 pos += 1
         out[t] = acc
     return out
+
+
+def num_threads():
+    return int(lib().ora_num_threads())
+
+
+def mode_product_fibres_inplace(n, k, M, X, f_begin, f_end, adjoint):
+    """X <- M []_k X restricted to fibres [f_begin, f_end) of mode k, in place
+    on the caller's array (no copy; used to time a bounded sample)."""
+    dims, dp = _dims(n)
+    X = _cvec(X)
+    Mb = _mat_colmajor(M)
+    lib().ora_mode_product_range(len(n), dp, int(k), Mb.ctypes.data, int(bool(adjoint)),
+                                 X.ctypes.data, int(f_begin), int(f_end))
+
+
+def sweep_inplace(n, T_list, CY, max_entries=-1):
+    """Literal sweep on the caller's array, the first max_entries entries of
+    Algorithm 3's order (all if -1).  Returns the multiply-subtract count."""
+    dims, dp = _dims(n)
+    CY = _cvec(CY)
+    P = _PtrArray(T_list)
+    return lib().ora_sweep_upper(len(n), dp, P.ptr, CY.ctypes.data, int(max_entries))
 
 
 def relative_residual(n, A_list, X, B):

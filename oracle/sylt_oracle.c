@@ -23,6 +23,7 @@
  * Algorithm 3's single loop with the mixed-radix counter of Algorithm 2.
  */
 #include <complex.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -39,6 +40,9 @@ static int64_t prod_range(const int64_t *n, int lo, int hi)
 }
 
 int64_t ora_numel(int N, const int64_t *n) { return prod_range(n, 0, N); }
+
+/* OpenMP threads the parallel loops of this library use. */
+int ora_num_threads(void) { return omp_get_max_threads(); }
 
 /*
  * Mode product along mode k (0-based), in place:

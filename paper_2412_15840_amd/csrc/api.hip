@@ -1,0 +1,669 @@
+// C ABI of libsylt: argument validation, plan construction (Schur factors,
+// separation, transform-pass and sweep-tile planning), and the solve drivers.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "sylt_internal.h"
+
+namespace sylt {
+
+int sweep_max_partial_block();
+
+namespace {
+
+constexpr int kSchurIterPerN = 30;
+constexpr int64_t kTransformTileCap = 8192;  // complex entries per transform tile
+constexpr int64_t kResidualTileCap = 5120;   // two tiles (X and accumulator), 160 KB
+constexpr int64_t kSweepTileCap = 8192;
+
+int status_of(hipError_t e)
+{
+    if (e == hipSuccess) return SYLT_OK;
+    if (e == hipErrorOutOfMemory) return SYLT_E_OUT_OF_MEMORY;
+    return SYLT_E_DEVICE;
+}
+
+#define SYLT_TRY(expr)                          \
+    do {                                        \
+        hipError_t _e = (expr);                 \
+        if (_e != hipSuccess) return status_of(_e); \
+    } while (0)
+
+int validate_shape(int N, const int64_t *n)
+{
+    if (N < 1 || !n) return SYLT_E_INVALID_ARG;
+    if (N > kMaxModes) return SYLT_E_UNSUPPORTED;
+    long double tot = 1;
+    for (int k = 0; k < N; ++k) {
+        if (n[k] < 1) return SYLT_E_INVALID_ARG;
+        if (n[k] > kMaxExtent) return SYLT_E_UNSUPPORTED;
+        tot *= (long double)n[k];
+    }
+    if (tot >= (long double)(1ull << 62)) return SYLT_E_UNSUPPORTED;
+    return SYLT_OK;
+}
+
+int64_t pow2_ceil(int64_t v)
+{
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+int ilog2(int64_t v)
+{
+    int s = 0;
+    while ((int64_t(1) << s) < v) ++s;
+    return s;
+}
+
+void plan_pass_list(sylt_plan_s &p, int64_t cap, std::vector<PassDesc> &out)
+{
+    out.clear();
+    const int M = p.M;
+    int a = 0;
+    while (a < M) {
+        int64_t Lin = 1;
+        for (int j = 0; j < a; ++j) Lin *= p.cdim[j];
+        // inner run: 16 entries (256 B) when that still fuses as many modes as
+        // 8 entries (128 B, one cache line) would; the whole low part if shorter
+        auto group_end = [&](int64_t lbv) {
+            int bb = a + 1;
+            int64_t GG = p.cdim[a];
+            while (bb < M && (int64_t)(bb - a) < kMaxGroup && lbv * GG * p.cdim[bb] <= cap)
+                GG *= p.cdim[bb++];
+            return bb;
+        };
+        int64_t lb = a == 0 ? 1 : std::min<int64_t>(16, pow2_ceil(Lin));
+        if (lb == 16 && group_end(8) > group_end(16)) lb = 8;
+        const int b = group_end(lb);
+        int64_t G = 1;
+        int maxn = 0;
+        for (int j = a; j < b; ++j) {
+            G *= p.cdim[j];
+            maxn = std::max(maxn, p.cdim[j]);
+        }
+        int64_t Rout = 1;
+        for (int j = b; j < M; ++j) Rout *= p.cdim[j];
+        PassDesc pd{};
+        pd.Lin = Lin;
+        pd.G = G;
+        pd.Rout = Rout;
+        pd.lb = (int)lb;
+        pd.lbshift = ilog2(lb);
+        pd.rb = (int)std::max<int64_t>(1, std::min<int64_t>(Rout, cap / (lb * G)));
+        pd.ntl = (Lin + lb - 1) / lb;
+        pd.ntr = (Rout + pd.rb - 1) / pd.rb;
+        pd.ng = b - a;
+        int64_t gs = 1;
+        pd.uniform_n = p.cdim[a];
+        for (int q = 0; q < pd.ng; ++q) {
+            const int j = a + q;
+            pd.gd[q] = p.cdim[j];
+            pd.gs[q] = (int)gs;
+            gs *= p.cdim[j];
+            pd.moff[q] = p.moff[p.cmode[j]];
+            if (p.cdim[j] != pd.uniform_n) pd.uniform_n = 0;
+        }
+        pd.maxn = maxn;
+        out.push_back(pd);
+        a = b;
+    }
+}
+
+}  // namespace
+
+void plan_passes(sylt_plan_s &p)
+{
+    plan_pass_list(p, kTransformTileCap, p.passes);
+    // the ping-pong (extent > 24) transform variant needs two tiles
+    for (PassDesc &pd : p.passes) {
+        if (pd.maxn > 24 && pd.lb * pd.G * pd.rb * 2 > kTransformTileCap) {
+            std::vector<PassDesc> half;
+            plan_pass_list(p, kTransformTileCap / 2, half);
+            p.passes = half;
+            break;
+        }
+    }
+    plan_pass_list(p, kResidualTileCap, p.rpasses);
+}
+
+size_t max_lds_bytes()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 65536;
+    return (size_t)v;
+}
+
+// Sweep tiling: choose the block size b_j of every compressed mode to
+// minimise the modelled time of the tile wavefront:
+//   HBM bytes ~ n_tot * 16 * (2 + sum_j (nb_j - 1)/2) * (coalescing penalty),
+//   plus a per-launch overhead for each tile level.
+namespace {
+
+double sweep_cost(const sylt_plan_s &p, const std::vector<int> &b)
+{
+    double R = 0.0;
+    int levels = 1;
+    for (int j = 0; j < p.M; ++j) {
+        const int nb = (p.cdim[j] + b[j] - 1) / b[j];
+        R += 0.5 * (nb - 1);
+        levels += nb - 1;
+    }
+    // contiguous run of a tile row, in complex128 entries
+    double run = 1;
+    for (int j = 0; j < p.M; ++j) {
+        run *= b[j];
+        if (b[j] < p.cdim[j]) break;
+    }
+    const double penalty = std::max(1.0, 8.0 / run);
+    const double bytes = (double)p.ntot * 16.0 * (2.0 + R) * penalty;
+    return bytes / 4.0e12 + levels * 6.0e-6;
+}
+
+}  // namespace
+
+int plan_sweep(sylt_plan_s &p)
+{
+    SweepPlan &sp = p.sweep;
+    SweepDesc &sd = sp.desc;
+    sd = SweepDesc{};
+    sd.M = p.M;
+    for (int k = 0; k < p.N; ++k)
+        if (p.n[k] == 1) sd.singoff[sd.nsing++] = p.moff[k];
+    const int M = p.M;
+    const int bmax = sweep_max_partial_block();
+    std::vector<int> b(M, 1);
+    const size_t lds_cap = std::min<size_t>(max_lds_bytes(), 160 * 1024);
+    auto tile_bytes = [&](const std::vector<int> &bb) {
+        int64_t S = 1, td = 0;
+        for (int j = 0; j < M; ++j) {
+            S *= bb[j];
+            td += (int64_t)bb[j] * bb[j];
+        }
+        return std::pair<int64_t, size_t>(S, (size_t)(S + td) * sizeof(double2));
+    };
+    // greedy: repeatedly take the move (a larger block on one mode) with the
+    // best modelled gain that still fits the LDS budget
+    for (;;) {
+        const double cur = sweep_cost(p, b);
+        double best_gain = 0.0;
+        int best_j = -1, best_b = 0;
+        for (int j = 0; j < M; ++j) {
+            const int d = p.cdim[j];
+            const int nb = (d + b[j] - 1) / b[j];
+            for (int nbn = nb - 1; nbn >= 1; --nbn) {
+                const int bn = (d + nbn - 1) / nbn;
+                if (bn < d && bn > bmax) continue;
+                std::vector<int> t = b;
+                t[j] = bn;
+                auto tb = tile_bytes(t);
+                if (tb.first > kSweepTileCap || tb.second > lds_cap) continue;
+                const double gain = (cur - sweep_cost(p, t)) / std::log2((double)bn / b[j]);
+                if (gain > best_gain) {
+                    best_gain = gain;
+                    best_j = j;
+                    best_b = bn;
+                }
+            }
+        }
+        if (best_j < 0) break;
+        b[best_j] = best_b;
+    }
+    int64_t S = 1, ntiles = 1;
+    int bitpos = 0, tdoff = 0, nll = 1, nlev = 1;
+    for (int j = 0; j < M; ++j) {
+        sd.d[j] = p.cdim[j];
+        sd.s[j] = p.cstride[j];
+        sd.b[j] = b[j];
+        sd.nb[j] = (p.cdim[j] + b[j] - 1) / b[j];
+        sd.ls[j] = (int)S;
+        sd.bitw[j] = b[j] > 1 ? ilog2(b[j]) : 0;
+        sd.bitoff[j] = bitpos;
+        bitpos += sd.bitw[j];
+        sd.tdoff[j] = tdoff;
+        tdoff += b[j] * b[j];
+        sd.moff[j] = p.moff[p.cmode[j]];
+        S *= b[j];
+        ntiles *= sd.nb[j];
+        nll += b[j] - 1;
+        nlev += sd.nb[j] - 1;
+    }
+    if (bitpos > 64 || ntiles > 0x7fffffff) return SYLT_E_UNSUPPORTED;
+    sd.S = (int)S;
+    sd.nll = nll;
+    sd.tdiag = tdoff;
+    sp.lds_bytes = (size_t)(S + tdoff) * sizeof(double2);
+    if (sp.lds_bytes > lds_cap) return SYLT_E_UNSUPPORTED;
+
+    // local tables of the full tile
+    std::vector<int64_t> goff(S);
+    std::vector<uint64_t> code(S);
+    std::vector<int> lev(S), llist(S), lloff(nll + 1, 0);
+    for (int64_t t = 0; t < S; ++t) {
+        int64_t rem = t, g = 0;
+        uint64_t c = 0;
+        int l = 0;
+        for (int j = 0; j < M; ++j) {
+            const int loc = (int)(rem % b[j]);
+            rem /= b[j];
+            g += (int64_t)loc * sd.s[j];
+            c |= (uint64_t)loc << sd.bitoff[j];
+            l += loc;
+        }
+        goff[t] = g;
+        code[t] = c;
+        lev[t] = l;
+        lloff[l + 1]++;
+    }
+    for (int l = 0; l < nll; ++l) lloff[l + 1] += lloff[l];
+    {
+        std::vector<int> fill(lloff.begin(), lloff.end() - 1);
+        for (int64_t t = 0; t < S; ++t) llist[fill[lev[t]]++] = (int)t;
+    }
+    // tiles sorted by block-index sum
+    std::vector<int> tlev(ntiles);
+    sp.level_off.assign(nlev + 1, 0);
+    for (int64_t id = 0; id < ntiles; ++id) {
+        int64_t rem = id;
+        int l = 0;
+        for (int j = 0; j < M; ++j) {
+            l += (int)(rem % sd.nb[j]);
+            rem /= sd.nb[j];
+        }
+        tlev[id] = l;
+        sp.level_off[l + 1]++;
+    }
+    for (int l = 0; l < nlev; ++l) sp.level_off[l + 1] += sp.level_off[l];
+    std::vector<int> tiles(ntiles);
+    {
+        std::vector<int64_t> fill(sp.level_off.begin(), sp.level_off.end() - 1);
+        for (int64_t id = 0; id < ntiles; ++id) tiles[fill[tlev[id]]++] = (int)id;
+    }
+    SYLT_TRY(hipMalloc(&sp.d_goff, S * sizeof(int64_t)));
+    SYLT_TRY(hipMalloc(&sp.d_code, S * sizeof(uint64_t)));
+    SYLT_TRY(hipMalloc(&sp.d_llist, S * sizeof(int)));
+    SYLT_TRY(hipMalloc(&sp.d_lloff, (nll + 1) * sizeof(int)));
+    SYLT_TRY(hipMalloc(&sp.d_tiles, std::max<int64_t>(1, ntiles) * sizeof(int)));
+    SYLT_TRY(hipMemcpy(sp.d_goff, goff.data(), S * sizeof(int64_t), hipMemcpyHostToDevice));
+    SYLT_TRY(hipMemcpy(sp.d_code, code.data(), S * sizeof(uint64_t), hipMemcpyHostToDevice));
+    SYLT_TRY(hipMemcpy(sp.d_llist, llist.data(), S * sizeof(int), hipMemcpyHostToDevice));
+    SYLT_TRY(hipMemcpy(sp.d_lloff, lloff.data(), (nll + 1) * sizeof(int), hipMemcpyHostToDevice));
+    SYLT_TRY(hipMemcpy(sp.d_tiles, tiles.data(), ntiles * sizeof(int), hipMemcpyHostToDevice));
+    return SYLT_OK;
+}
+
+}  // namespace sylt
+
+using namespace sylt;
+
+namespace {
+
+void free_plan(sylt_plan_s *p)
+{
+    if (!p) return;
+    hipDeviceSynchronize();
+    hipFree(p->dA);
+    hipFree(p->dU);
+    hipFree(p->dUh);
+    hipFree(p->dT);
+    hipFree(p->dU32);
+    hipFree(p->dUh32);
+    hipFree(p->dStatus);
+    hipFree(p->dScratch);
+    hipFree(p->sweep.d_tiles);
+    hipFree(p->sweep.d_goff);
+    hipFree(p->sweep.d_code);
+    hipFree(p->sweep.d_llist);
+    hipFree(p->sweep.d_lloff);
+    delete p;
+}
+
+// Shape bookkeeping and device allocation shared by both plan constructors.
+int init_plan(sylt_plan_s *p, int N, const int64_t *n)
+{
+    SYLT_TRY(hipGetDevice(&p->device));
+    p->N = N;
+    p->n.assign(n, n + N);
+    p->ntot = 1;
+    p->moff.resize(N);
+    p->mtotal = 0;
+    int64_t stride = 1;
+    for (int k = 0; k < N; ++k) {
+        p->ntot *= n[k];
+        p->moff[k] = p->mtotal;
+        p->mtotal += n[k] * n[k];
+        if (n[k] > 1) {
+            p->cmode.push_back(k);
+            p->cdim.push_back((int)n[k]);
+            p->cstride.push_back(stride);
+        }
+        stride *= n[k];
+    }
+    p->M = (int)p->cmode.size();
+    const size_t mb = p->mtotal * sizeof(double2);
+    SYLT_TRY(hipMalloc(&p->dA, mb));
+    SYLT_TRY(hipMalloc(&p->dU, mb));
+    SYLT_TRY(hipMalloc(&p->dUh, mb));
+    SYLT_TRY(hipMalloc(&p->dT, mb));
+    SYLT_TRY(hipMalloc(&p->dU32, p->mtotal * sizeof(float2)));
+    SYLT_TRY(hipMalloc(&p->dUh32, p->mtotal * sizeof(float2)));
+    SYLT_TRY(hipMalloc(&p->dStatus, std::max(1, N) * sizeof(int)));
+    SYLT_TRY(hipMemset(p->dStatus, 0, std::max(1, N) * sizeof(int)));
+    plan_passes(*p);
+    int64_t maxt = 1;
+    for (const PassDesc &pd : p->rpasses) maxt = std::max<int64_t>(maxt, pd.ntl * pd.ntr);
+    p->scratch_bytes = (size_t)(std::max<int64_t>(2 * maxt, 4096) + 64) * sizeof(double);
+    SYLT_TRY(hipMalloc(&p->dScratch, p->scratch_bytes));
+    return plan_sweep(*p);
+}
+
+// separation into the tail of the scratch, then one synchronisation
+int finish_plan(sylt_plan_s *p, hipStream_t s, bool check_schur)
+{
+    SYLT_TRY(launch_prepare_factors(*p, s));
+    double *d_sep = p->dScratch + (p->scratch_bytes / sizeof(double) - 8);
+    SYLT_TRY(launch_separation(*p, d_sep, s));
+    std::vector<int> st(p->N, 0);
+    SYLT_TRY(hipMemcpyAsync(&p->sep, d_sep, sizeof(double), hipMemcpyDeviceToHost, s));
+    SYLT_TRY(hipMemcpyAsync(st.data(), p->dStatus, p->N * sizeof(int), hipMemcpyDeviceToHost, s));
+    SYLT_TRY(hipStreamSynchronize(s));
+    if (check_schur)
+        for (int k = 0; k < p->N; ++k)
+            if (st[k]) return SYLT_E_NO_CONVERGENCE;
+    if (!(p->sep > 0.0)) return SYLT_E_SINGULAR;
+    return SYLT_OK;
+}
+
+int check_ptrs(int N, const double *const *P)
+{
+    if (!P) return SYLT_E_INVALID_ARG;
+    for (int k = 0; k < N; ++k)
+        if (!P[k]) return SYLT_E_INVALID_ARG;
+    return SYLT_OK;
+}
+
+int64_t mixed_workspace(const sylt_plan_s *p)
+{
+    const int64_t r64 = p->rpasses.size() > 1 ? p->ntot * (int64_t)sizeof(double2) : 0;
+    return r64 + p->ntot * (int64_t)sizeof(float2) + 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sylt_version(void) { return 100; }
+
+const char *sylt_status_string(int code)
+{
+    switch (code) {
+        case SYLT_OK: return "success";
+        case SYLT_E_INVALID_ARG: return "invalid argument";
+        case SYLT_E_SINGULAR: return "singular: an eigenvalue sum is zero";
+        case SYLT_E_NO_CONVERGENCE: return "iteration did not converge";
+        case SYLT_E_OUT_OF_MEMORY: return "out of device memory";
+        case SYLT_E_DEVICE: return "HIP runtime error";
+        case SYLT_E_UNSUPPORTED: return "outside the supported limits";
+        case SYLT_E_WORKSPACE: return "workspace missing or too small";
+        default: return "unknown status";
+    }
+}
+
+int sylt_schur_factor(int N, const int64_t *n, const double *const *A, void *stream, sylt_plan *out)
+{
+    if (!out) return SYLT_E_INVALID_ARG;
+    *out = nullptr;
+    int st = validate_shape(N, n);
+    if (st) return st;
+    if ((st = check_ptrs(N, A))) return st;
+    sylt_plan_s *p = new (std::nothrow) sylt_plan_s();
+    if (!p) return SYLT_E_OUT_OF_MEMORY;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = init_plan(p, N, n);
+    if (!st) {
+        for (int k = 0; k < N && !st; ++k)
+            st = status_of(hipMemcpyAsync(p->dA + p->moff[k], A[k], n[k] * n[k] * sizeof(double2),
+                                          hipMemcpyDeviceToDevice, s));
+    }
+    if (!st) st = status_of(launch_schur(*p, kSchurIterPerN, s));
+    p->has_A = true;
+    if (!st) st = finish_plan(p, s, true);
+    if (st) {
+        free_plan(p);
+        return st;
+    }
+    *out = p;
+    return SYLT_OK;
+}
+
+int sylt_plan_from_factors(int N, const int64_t *n, const double *const *A, const double *const *U,
+                           const double *const *T, void *stream, sylt_plan *out)
+{
+    if (!out) return SYLT_E_INVALID_ARG;
+    *out = nullptr;
+    int st = validate_shape(N, n);
+    if (st) return st;
+    if ((st = check_ptrs(N, U)) || (st = check_ptrs(N, T))) return st;
+    if (A && (st = check_ptrs(N, A))) return st;
+    sylt_plan_s *p = new (std::nothrow) sylt_plan_s();
+    if (!p) return SYLT_E_OUT_OF_MEMORY;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = init_plan(p, N, n);
+    for (int k = 0; k < N && !st; ++k) {
+        const size_t bytes = n[k] * n[k] * sizeof(double2);
+        st = status_of(hipMemcpyAsync(p->dU + p->moff[k], U[k], bytes, hipMemcpyDeviceToDevice, s));
+        if (!st)
+            st = status_of(hipMemcpyAsync(p->dT + p->moff[k], T[k], bytes, hipMemcpyDeviceToDevice, s));
+        if (!st && A)
+            st = status_of(hipMemcpyAsync(p->dA + p->moff[k], A[k], bytes, hipMemcpyDeviceToDevice, s));
+    }
+    p->has_A = A != nullptr;
+    if (!st) st = finish_plan(p, s, false);
+    if (st) {
+        free_plan(p);
+        return st;
+    }
+    *out = p;
+    return SYLT_OK;
+}
+
+int sylt_plan_get_factors(sylt_plan p, int k, double *U, double *T, void *stream)
+{
+    if (!p || k < 0 || k >= p->N) return SYLT_E_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t bytes = p->n[k] * p->n[k] * sizeof(double2);
+    if (U) SYLT_TRY(hipMemcpyAsync(U, p->dU + p->moff[k], bytes, hipMemcpyDeviceToDevice, s));
+    if (T) SYLT_TRY(hipMemcpyAsync(T, p->dT + p->moff[k], bytes, hipMemcpyDeviceToDevice, s));
+    return SYLT_OK;
+}
+
+int sylt_plan_separation(sylt_plan p, double *sep)
+{
+    if (!p || !sep) return SYLT_E_INVALID_ARG;
+    *sep = p->sep;
+    return SYLT_OK;
+}
+
+int sylt_plan_describe(sylt_plan p, char *buf, size_t len)
+{
+    if (!p || !buf || len == 0) return SYLT_E_INVALID_ARG;
+    std::string s = "{\"N\":" + std::to_string(p->N) + ",\"n\":[";
+    for (int k = 0; k < p->N; ++k) s += (k ? "," : "") + std::to_string(p->n[k]);
+    s += "],\"ntot\":" + std::to_string(p->ntot);
+    char sep[64];
+    snprintf(sep, sizeof sep, "%.17g", p->sep);
+    s += ",\"sep\":" + std::string(sep);
+    auto passes = [&](const char *name, const std::vector<PassDesc> &v) {
+        s += ",\"" + std::string(name) + "\":[";
+        for (size_t i = 0; i < v.size(); ++i) {
+            const PassDesc &d = v[i];
+            s += (i ? "," : "") + std::string("{\"extents\":[");
+            for (int q = 0; q < d.ng; ++q) s += (q ? "," : "") + std::to_string(d.gd[q]);
+            s += "],\"Lin\":" + std::to_string(d.Lin) + ",\"G\":" + std::to_string(d.G) +
+                 ",\"Rout\":" + std::to_string(d.Rout) + ",\"lb\":" + std::to_string(d.lb) +
+                 ",\"rb\":" + std::to_string(d.rb) + ",\"tiles\":" + std::to_string(d.ntl * d.ntr) +
+                 "}";
+        }
+        s += "]";
+    };
+    passes("transform_passes", p->passes);
+    passes("residual_passes", p->rpasses);
+    const SweepDesc &sd = p->sweep.desc;
+    int launches = 0;
+    for (size_t l = 0; l + 1 < p->sweep.level_off.size(); ++l)
+        launches += p->sweep.level_off[l + 1] > p->sweep.level_off[l];
+    s += ",\"sweep\":{\"block\":[";
+    for (int j = 0; j < sd.M; ++j) s += (j ? "," : "") + std::to_string(sd.b[j]);
+    s += "],\"tile_entries\":" + std::to_string(sd.S) +
+         ",\"tiles\":" + std::to_string(p->sweep.level_off.empty() ? 0 : p->sweep.level_off.back()) +
+         ",\"tile_levels\":" + std::to_string(launches) + ",\"local_levels\":" + std::to_string(sd.nll) +
+         ",\"lds_bytes\":" + std::to_string(p->sweep.lds_bytes) + "}}";
+    const size_t n = std::min(len - 1, s.size());
+    memcpy(buf, s.data(), n);
+    buf[n] = '\0';
+    return s.size() < len ? SYLT_OK : SYLT_E_INVALID_ARG;
+}
+
+int sylt_plan_destroy(sylt_plan p)
+{
+    if (!p) return SYLT_E_INVALID_ARG;
+    free_plan(p);
+    return SYLT_OK;
+}
+
+int64_t sylt_workspace_bytes(sylt_plan p, int precision)
+{
+    if (!p) return SYLT_E_INVALID_ARG;
+    if (precision == SYLT_FP64) return (int64_t)std::max<size_t>(256, grad_A_workspace(*p) + 256);
+    if (precision == SYLT_MIXED) return mixed_workspace(p);
+    return SYLT_E_INVALID_ARG;
+}
+
+int sylt_transform(sylt_plan p, int dir, int precision, void *X, void *stream)
+{
+    if (!p || !X) return SYLT_E_INVALID_ARG;
+    if (dir != SYLT_TO_SCHUR && dir != SYLT_FROM_SCHUR) return SYLT_E_INVALID_ARG;
+    if (precision != SYLT_FP64 && precision != SYLT_MIXED) return SYLT_E_INVALID_ARG;
+    return status_of(launch_transform(*p, dir, precision, X, static_cast<hipStream_t>(stream)));
+}
+
+int sylt_sweep(sylt_plan p, int op, int precision, void *CY, void *stream)
+{
+    if (!p || !CY) return SYLT_E_INVALID_ARG;
+    if (op != SYLT_OP_N && op != SYLT_OP_C) return SYLT_E_INVALID_ARG;
+    if (precision != SYLT_FP64 && precision != SYLT_MIXED) return SYLT_E_INVALID_ARG;
+    return status_of(launch_sweep(*p, op, precision, CY, static_cast<hipStream_t>(stream)));
+}
+
+int sylt_residual(sylt_plan p, const double *B, const double *X, double *R, double *norms,
+                  void *stream)
+{
+    if (!p || !B || !X || !R || !p->has_A) return SYLT_E_INVALID_ARG;
+    if (p->M == 0) return SYLT_E_UNSUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double *d_norms = p->dScratch + (p->scratch_bytes / sizeof(double) - 4);
+    SYLT_TRY(launch_residual(*p, reinterpret_cast<const double2 *>(B),
+                             reinterpret_cast<const double2 *>(X), reinterpret_cast<double2 *>(R),
+                             nullptr, norms ? d_norms : nullptr, s));
+    if (norms) {
+        SYLT_TRY(hipMemcpyAsync(norms, d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        SYLT_TRY(hipStreamSynchronize(s));
+    }
+    return SYLT_OK;
+}
+
+int sylt_solve(sylt_plan p, const sylt_opts *o, const double *B, double *X, void *ws,
+               size_t ws_bytes, void *stream, sylt_info *info)
+{
+    if (!p || !B || !X) return SYLT_E_INVALID_ARG;
+    const int precision = o ? o->precision : SYLT_FP64;
+    if (precision != SYLT_FP64 && precision != SYLT_MIXED) return SYLT_E_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double2 *Xc = reinterpret_cast<double2 *>(X);
+    const double2 *Bc = reinterpret_cast<const double2 *>(B);
+    if (info) {
+        info->status = SYLT_OK;
+        info->iterations = 0;
+        info->rel_residual = -1.0;
+        info->sep = p->sep;
+    }
+    if (precision == SYLT_FP64) {
+        if (Xc != Bc) SYLT_TRY(launch_copy_c128(Xc, Bc, p->ntot, s));
+        SYLT_TRY(launch_transform(*p, SYLT_TO_SCHUR, SYLT_FP64, Xc, s));
+        SYLT_TRY(launch_sweep(*p, SYLT_OP_N, SYLT_FP64, Xc, s));
+        SYLT_TRY(launch_transform(*p, SYLT_FROM_SCHUR, SYLT_FP64, Xc, s));
+        if (info) {
+            info->iterations = 1;
+            SYLT_TRY(hipStreamSynchronize(s));
+        }
+        return SYLT_OK;
+    }
+    // MIXED: iterative refinement with FP32 transforms
+    if (!p->has_A || p->M == 0 || Xc == Bc || o->max_iter < 1 || !(o->rtol >= 0.0))
+        return SYLT_E_INVALID_ARG;
+    if (!ws || (int64_t)ws_bytes < mixed_workspace(p)) return SYLT_E_WORKSPACE;
+    char *w = static_cast<char *>(ws);
+    double2 *R64 = nullptr;
+    if (p->rpasses.size() > 1) {
+        R64 = reinterpret_cast<double2 *>(w);
+        w += p->ntot * sizeof(double2);
+    }
+    float2 *R32 = reinterpret_cast<float2 *>(w);
+    double *d_norms = p->dScratch + (p->scratch_bytes / sizeof(double) - 4);
+    SYLT_TRY(launch_convert_c128_c64(R32, Bc, p->ntot, s));
+    int it = 0;
+    double rel = -1.0;
+    int st = SYLT_E_NO_CONVERGENCE;
+    for (;;) {
+        SYLT_TRY(launch_transform(*p, SYLT_TO_SCHUR, SYLT_MIXED, R32, s));
+        SYLT_TRY(launch_sweep(*p, SYLT_OP_N, SYLT_MIXED, R32, s));
+        SYLT_TRY(launch_transform(*p, SYLT_FROM_SCHUR, SYLT_MIXED, R32, s));
+        SYLT_TRY(launch_axpy_c64(Xc, R32, p->ntot, it == 0, s));
+        ++it;
+        SYLT_TRY(launch_residual(*p, Bc, Xc, R64, R32, d_norms, s));
+        double nrm[2];
+        SYLT_TRY(hipMemcpyAsync(nrm, d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        SYLT_TRY(hipStreamSynchronize(s));
+        rel = nrm[1] > 0.0 ? std::sqrt(nrm[0] / nrm[1]) : std::sqrt(nrm[0]);
+        if (rel <= o->rtol) {
+            st = SYLT_OK;
+            break;
+        }
+        if (it >= o->max_iter || !std::isfinite(rel)) break;
+    }
+    if (info) {
+        info->status = st;
+        info->iterations = it;
+        info->rel_residual = rel;
+    }
+    return st;
+}
+
+int sylt_solve_backward(sylt_plan p, const double *X, const double *GX, double *GB,
+                        double *const *GA, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!p || !X || !GX || !GB) return SYLT_E_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double2 *G = reinterpret_cast<double2 *>(GB);
+    if (GB != GX) SYLT_TRY(launch_copy_c128(G, reinterpret_cast<const double2 *>(GX), p->ntot, s));
+    SYLT_TRY(launch_transform(*p, SYLT_TO_SCHUR, SYLT_FP64, G, s));
+    SYLT_TRY(launch_sweep(*p, SYLT_OP_C, SYLT_FP64, G, s));
+    SYLT_TRY(launch_transform(*p, SYLT_FROM_SCHUR, SYLT_FP64, G, s));
+    if (GA) {
+        bool any = false;
+        for (int k = 0; k < p->N; ++k) any |= GA[k] != nullptr;
+        if (any) {
+            if (!ws || ws_bytes < grad_A_workspace(*p)) return SYLT_E_WORKSPACE;
+            SYLT_TRY(launch_grad_A(*p, G, reinterpret_cast<const double2 *>(X),
+                                   reinterpret_cast<double2 *const *>(GA), ws, ws_bytes, s));
+        }
+    }
+    return SYLT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,273 @@
+// Complex Schur factorisation A = U T U^* on the device (Section 2 of the
+// paper: every A_j is reduced to upper-triangular T_j by a unitary U_j).
+//
+// One 64-lane workgroup per matrix (n <= 64), both H and U resident in LDS:
+//  1. Householder reduction to upper Hessenberg form, accumulating U.
+//  2. Single-shift complex QR iteration on the active unreduced window with a
+//     Wilkinson shift (exceptional shifts every 10 iterations without
+//     deflation), as in Golub & Van Loan, Matrix Computations, Sections
+//     7.4-7.5.  Each step factors H_w - mu I with Givens rotations, multiplies
+//     back and restores the shift; rotations are also applied to the parts of
+//     H outside the window (so the full triangular T results) and to U.
+//  3. T = H with its strictly lower part set to exactly zero.
+// Rows / columns of every rotation and reflection are spread over the lanes.
+#include "sylt_internal.h"
+
+namespace sylt {
+namespace {
+
+struct SchurJobs {
+    int count;
+    int n[kMaxModes];
+    int64_t off[kMaxModes];
+};
+
+__device__ inline void givens(double2 a, double2 b, double &c, double2 &s)
+{
+    // [c s; -conj(s) c] [a; b] = [r; 0] with real c and c^2 + |s|^2 = 1
+    if (b.x == 0.0 && b.y == 0.0) {
+        c = 1.0;
+        s = cd(0.0, 0.0);
+        return;
+    }
+    const double absb = cabs2(b);
+    if (a.x == 0.0 && a.y == 0.0) {
+        c = 0.0;
+        s = cd(b.x / absb, -b.y / absb);
+        return;
+    }
+    const double absa = cabs2(a);
+    const double rho = hypot(absa, absb);
+    c = absa / rho;
+    const double2 ph = cd(a.x / absa, a.y / absa);
+    s = cscale(cmul(ph, cconj(b)), 1.0 / rho);
+}
+
+__global__ void __launch_bounds__(64) schur_kernel(SchurJobs jobs, const double2 *__restrict__ A,
+                                                   double2 *__restrict__ Uout,
+                                                   double2 *__restrict__ Tout, int *status,
+                                                   int max_iter_per_n)
+{
+    extern __shared__ double2 smem[];
+    const int job = blockIdx.x;
+    const int n = jobs.n[job];
+    const int64_t off = jobs.off[job];
+    const int tid = threadIdx.x;
+    double2 *H = smem;                  // n x n, column-major: H[i + n*j]
+    double2 *Q = smem + n * n;
+    double2 *v = Q + n * n;             // Householder vector (n)
+    double2 *gs = v + n;                // rotation sines (n)
+    double *gc = reinterpret_cast<double *>(gs + n);  // rotation cosines (n)
+#define HH(i, j) H[(i) + n * (j)]
+#define QQ(i, j) Q[(i) + n * (j)]
+
+    for (int idx = tid; idx < n * n; idx += 64) {
+        H[idx] = A[off + idx];
+        Q[idx] = cd((idx % n) == (idx / n) ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+
+    // ---- 1. Hessenberg reduction
+    for (int k = 0; k + 2 < n; ++k) {
+        double sig = 0.0;
+        for (int r = k + 2; r < n; ++r) {
+            const double2 h = HH(r, k);
+            sig += h.x * h.x + h.y * h.y;
+        }
+        if (sig == 0.0) continue;  // uniform: every lane read the same values
+        const double2 x0 = HH(k + 1, k);
+        const double ax0 = cabs2(x0);
+        const double alpha = sqrt(ax0 * ax0 + sig);
+        const double2 ph = ax0 > 0.0 ? cd(x0.x / ax0, x0.y / ax0) : cd(1.0, 0.0);
+        const double2 v0 = cadd(x0, cscale(ph, alpha));
+        const double tau = 2.0 / (v0.x * v0.x + v0.y * v0.y + sig);
+        const double2 beta = cscale(ph, -alpha);
+        __syncthreads();
+        for (int r = k + 1 + tid; r < n; r += 64) v[r] = (r == k + 1) ? v0 : HH(r, k);
+        __syncthreads();
+        // left: rows k+1.., columns k..n-1:  H <- (I - tau v v^*) H
+        for (int c = k + tid; c < n; c += 64) {
+            double2 w = cd(0.0, 0.0);
+            for (int r = k + 1; r < n; ++r) w = cmac_conj(w, v[r], HH(r, c));
+            w = cscale(w, tau);
+            for (int r = k + 1; r < n; ++r) HH(r, c) = csub(HH(r, c), cmul(v[r], w));
+        }
+        __syncthreads();
+        // right: all rows, columns k+1..:  H <- H (I - tau v v^*),  U <- U (I - tau v v^*)
+        for (int r = tid; r < n; r += 64) {
+            double2 w = cd(0.0, 0.0);
+            double2 wq = cd(0.0, 0.0);
+            for (int c = k + 1; c < n; ++c) {
+                w = cmac(w, HH(r, c), v[c]);
+                wq = cmac(wq, QQ(r, c), v[c]);
+            }
+            w = cscale(w, tau);
+            wq = cscale(wq, tau);
+            for (int c = k + 1; c < n; ++c) {
+                HH(r, c) = csub(HH(r, c), cmul(w, cconj(v[c])));
+                QQ(r, c) = csub(QQ(r, c), cmul(wq, cconj(v[c])));
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            HH(k + 1, k) = beta;
+            for (int r = k + 2; r < n; ++r) HH(r, k) = cd(0.0, 0.0);
+        }
+        __syncthreads();
+    }
+
+    // ---- 2. shifted QR on the Hessenberg matrix
+    const double eps = 2.220446049250313e-16;
+    int hi = n - 1, iter = 0, total = 0, failed = 0;
+    const int maxit = max_iter_per_n * n;
+    while (hi > 0) {
+        // deflation scan (every lane computes the same, reading the same LDS)
+        int lo = hi;
+        while (lo > 0) {
+            const double2 h = HH(lo, lo - 1);
+            double tst = cabs1(HH(lo - 1, lo - 1)) + cabs1(HH(lo, lo));
+            if (tst == 0.0) tst = 1.0;
+            if (cabs1(h) <= eps * tst) break;
+            --lo;
+        }
+        __syncthreads();
+        if (lo > 0 && tid == 0) HH(lo, lo - 1) = cd(0.0, 0.0);
+        __syncthreads();
+        if (lo == hi) {
+            --hi;
+            iter = 0;
+            continue;
+        }
+        if (++total > maxit) {
+            failed = 1;
+            break;
+        }
+        ++iter;
+        double2 mu;
+        const double2 hd = HH(hi, hi);
+        if (iter % 10 == 0) {
+            // exceptional shift: perturb away from a possibly stagnating shift
+            mu = cadd(hd, cd(0.75 * cabs1(HH(hi, hi - 1)), 0.0));
+        } else {
+            const double2 a = HH(hi - 1, hi - 1), b = HH(hi - 1, hi), c = HH(hi, hi - 1);
+            const double2 p = cscale(csub(a, hd), 0.5);
+            const double2 bc = cmul(b, c);
+            const double2 disc = csqrt_(cadd(cmul(p, p), bc));
+            const double2 s1 = cadd(p, disc), s2 = csub(p, disc);
+            const double2 den = cabs2(s1) >= cabs2(s2) ? s1 : s2;
+            mu = (den.x == 0.0 && den.y == 0.0) ? hd : csub(hd, cdiv(bc, den));
+        }
+        __syncthreads();
+        for (int t = lo + tid; t <= hi; t += 64) HH(t, t) = csub(HH(t, t), mu);
+        __syncthreads();
+        // H_w - mu I = Q R : rotations from the left, applied across to column n-1
+        for (int k = lo; k < hi; ++k) {
+            double c;
+            double2 s;
+            givens(HH(k, k), HH(k + 1, k), c, s);
+            if (tid == 0) {
+                gc[k] = c;
+                gs[k] = s;
+            }
+            __syncthreads();
+            for (int col = k + tid; col < n; col += 64) {
+                const double2 x = HH(k, col), y = HH(k + 1, col);
+                HH(k, col) = cadd(cscale(x, c), cmul(s, y));
+                HH(k + 1, col) = csub(cscale(y, c), cmul(cconj(s), x));
+            }
+            __syncthreads();
+            if (tid == 0) HH(k + 1, k) = cd(0.0, 0.0);
+            __syncthreads();
+        }
+        // R Q : rotations from the right on rows 0..k+1, and on U
+        for (int k = lo; k < hi; ++k) {
+            const double c = gc[k];
+            const double2 s = gs[k];
+            for (int r = tid; r <= k + 1; r += 64) {
+                const double2 x = HH(r, k), y = HH(r, k + 1);
+                HH(r, k) = cadd(cscale(x, c), cmul(cconj(s), y));
+                HH(r, k + 1) = csub(cscale(y, c), cmul(s, x));
+            }
+            for (int r = tid; r < n; r += 64) {
+                const double2 x = QQ(r, k), y = QQ(r, k + 1);
+                QQ(r, k) = cadd(cscale(x, c), cmul(cconj(s), y));
+                QQ(r, k + 1) = csub(cscale(y, c), cmul(s, x));
+            }
+            __syncthreads();
+        }
+        for (int t = lo + tid; t <= hi; t += 64) HH(t, t) = cadd(HH(t, t), mu);
+        __syncthreads();
+    }
+
+    // ---- 3. write U and T (strictly lower part of T exactly zero)
+    for (int idx = tid; idx < n * n; idx += 64) {
+        const int i = idx % n, j = idx / n;
+        Uout[off + idx] = Q[idx];
+        Tout[off + idx] = (i > j) ? cd(0.0, 0.0) : H[idx];
+    }
+    if (tid == 0) status[job] = failed;
+#undef HH
+#undef QQ
+}
+
+// U^* (conjugate transpose) and complex64 copies of U and U^*; singleton modes
+// get U = 1, T = A.
+struct PrepJobs {
+    int count;
+    int n[kMaxModes];
+    int64_t off[kMaxModes];
+};
+
+__global__ void prepare_factors_kernel(PrepJobs jobs, const double2 *__restrict__ U,
+                                       double2 *__restrict__ Uh, float2 *__restrict__ U32,
+                                       float2 *__restrict__ Uh32)
+{
+    const int job = blockIdx.x;
+    const int n = jobs.n[job];
+    const int64_t off = jobs.off[job];
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+        const int i = idx % n, j = idx / n;
+        const double2 u = U[off + idx];
+        const double2 ut = U[off + j + (int64_t)n * i];
+        Uh[off + idx] = cconj(ut);
+        U32[off + idx] = make_float2((float)u.x, (float)u.y);
+        Uh32[off + idx] = make_float2((float)ut.x, (float)-ut.y);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_schur(const sylt_plan_s &p, int max_iter_per_n, hipStream_t s)
+{
+    SchurJobs jobs{};
+    int nmax = 1;
+    for (int k = 0; k < p.N; ++k) {  // singleton modes give U = 1, T = A
+        jobs.n[jobs.count] = (int)p.n[k];
+        jobs.off[jobs.count] = p.moff[k];
+        ++jobs.count;
+        nmax = std::max(nmax, (int)p.n[k]);
+    }
+    if (jobs.count == 0) return hipSuccess;
+    const size_t lds = (size_t)(2 * nmax * nmax + 2 * nmax) * sizeof(double2) + nmax * sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void *)schur_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(schur_kernel, dim3(jobs.count), dim3(64), lds, s, jobs, p.dA, p.dU, p.dT,
+                       p.dStatus, max_iter_per_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare_factors(const sylt_plan_s &p, hipStream_t s)
+{
+    PrepJobs jobs{};
+    for (int k = 0; k < p.N; ++k) {
+        jobs.n[jobs.count] = (int)p.n[k];
+        jobs.off[jobs.count] = p.moff[k];
+        ++jobs.count;
+    }
+    hipLaunchKernelGGL(prepare_factors_kernel, dim3(jobs.count), dim3(256), 0, s, jobs, p.dU,
+                       p.dUh, p.dU32, p.dUh32);
+    return hipGetLastError();
+}
+
+}  // namespace sylt

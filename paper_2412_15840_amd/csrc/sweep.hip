@@ -1,0 +1,213 @@
+// The triangular sweep on gfx950 (Section 2: eq. e:yi1i2iN, solved in any
+// order that computes every dependency first).
+//
+// Entry y_i depends only on entries that are larger in exactly one index
+// (i_j -> k > i_j).  The (non-singleton) modes are cut into blocks of b_j
+// indices; a tile is a product of blocks and holds at most ~8k entries, so it
+// lives in LDS.  A tile P depends on the tiles P + (q - P_j) e_j, q > P_j, so
+// all tiles with the same block-index sum are independent: they form one
+// launch, and launches run from the largest block-index sum down (a wavefront
+// over tile hyperplanes).  Inside a workgroup:
+//   1. the tile of C and the diagonal blocks of every T_j go to LDS;
+//   2. for every mode j, the part of the sum over k > i_j that lies in tiles
+//      above along j is a small contraction
+//        C_tile -= T_j[rows of P_j, k >= end of P_j] x_j Y[..., k, ...],
+//      computed by lanes that each own one cross-section position: they load
+//      each needed Y entry once from HBM and update all b_j rows in registers,
+//      with the T_j coefficients wave-uniform;
+//   3. the tile itself is solved by local hyperplanes (sum of local indices,
+//      descending), one barrier per local level, dividing by the eigenvalue
+//      sums t_{1,i_1 i_1} + ... + t_{N,i_N i_N} (+ the singleton scalars);
+//   4. the tile is written back in place.
+// The adjoint operator (sum_j T_j^* x_j, lower triangular) runs the same
+// machinery mirrored: ascending block sums, pulls from tiles below, conjugated
+// coefficients.
+#include "sylt_internal.h"
+
+namespace sylt {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kBmax = 8;   // largest block of a partially tiled mode
+
+struct TileState {
+    int o[kMaxModes];
+    int e[kMaxModes];
+    int64_t base;
+    int ragged;
+    double2 shift;
+};
+
+__device__ __forceinline__ bool entry_valid(uint64_t c, const SweepDesc &sd, const TileState &ts)
+{
+    for (int j = 0; j < sd.M; ++j) {
+        const int w = sd.bitw[j];
+        if (w == 0) continue;
+        const int loc = (int)((c >> sd.bitoff[j]) & ((1ull << w) - 1ull));
+        if (loc >= ts.e[j]) return false;
+    }
+    return true;
+}
+
+template <typename V, bool ADJ>
+__global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
+    V *__restrict__ X, const double2 *__restrict__ Tbuf, SweepDesc sd,
+    const int *__restrict__ tiles, const int64_t *__restrict__ goff,
+    const uint64_t *__restrict__ code, const int *__restrict__ llist,
+    const int *__restrict__ lloff)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double2 *tile = reinterpret_cast<double2 *>(smem_raw);
+    double2 *tdiag = tile + sd.S;
+    __shared__ TileState ts;
+
+    if (threadIdx.x == 0) {
+        int rem = tiles[blockIdx.x];
+        int64_t base = 0;
+        int ragged = 0;
+        for (int j = 0; j < sd.M; ++j) {
+            const int P = rem % sd.nb[j];
+            rem /= sd.nb[j];
+            ts.o[j] = P * sd.b[j];
+            ts.e[j] = min(sd.b[j], sd.d[j] - ts.o[j]);
+            ragged |= ts.e[j] < sd.b[j];
+            base += (int64_t)ts.o[j] * sd.s[j];
+        }
+        double2 sh = make_double2(0.0, 0.0);
+        for (int i = 0; i < sd.nsing; ++i) sh = cadd(sh, Tbuf[sd.singoff[i]]);
+        ts.base = base;
+        ts.ragged = ragged;
+        ts.shift = ADJ ? cconj(sh) : sh;
+    }
+    __syncthreads();
+
+    // 1. diagonal blocks of T_j and the tile of C
+    for (int j = 0; j < sd.M; ++j) {
+        const int b = sd.b[j], e = ts.e[j], o = ts.o[j], d = sd.d[j];
+        const double2 *Tj = Tbuf + sd.moff[j];
+        for (int idx = threadIdx.x; idx < b * b; idx += blockDim.x) {
+            const int r = idx % b, c = idx / b;
+            tdiag[sd.tdoff[j] + idx] =
+                (r < e && c < e) ? Tj[(o + r) + (int64_t)d * (o + c)] : make_double2(0.0, 0.0);
+        }
+    }
+    for (int t = threadIdx.x; t < sd.S; t += blockDim.x) {
+        if (ts.ragged && !entry_valid(code[t], sd, ts)) continue;
+        tile[t] = to_d2<V>(X[ts.base + goff[t]]);
+    }
+    __syncthreads();
+
+    // 2. contributions of the tiles above (below, for the adjoint) along each mode
+    for (int j = 0; j < sd.M; ++j) {
+        const int o = __builtin_amdgcn_readfirstlane(ts.o[j]);
+        const int e = __builtin_amdgcn_readfirstlane(ts.e[j]);
+        const int d = sd.d[j];
+        const int k0 = ADJ ? 0 : o + e;
+        const int k1 = ADJ ? o : d;
+        if (k0 >= k1) continue;  // uniform
+        const int b = sd.b[j], lsj = sd.ls[j];
+        const int64_t sj = sd.s[j];
+        const int cs = sd.S / b;
+        const double2 *Tj = Tbuf + sd.moff[j];
+        for (int c = threadIdx.x; c < cs; c += blockDim.x) {
+            const int t0 = (c % lsj) + (c / lsj) * lsj * b;
+            if (ts.ragged && !entry_valid(code[t0], sd, ts)) continue;
+            const int64_t g0 = ts.base + goff[t0];  // entry with i_j = o
+            double2 acc[kBmax];
+#pragma unroll
+            for (int r = 0; r < kBmax; ++r) acc[r] = make_double2(0.0, 0.0);
+            for (int k = k0; k < k1; ++k) {
+                const double2 y = to_d2<V>(X[g0 + (int64_t)(k - o) * sj]);
+#pragma unroll
+                for (int r = 0; r < kBmax; ++r) {
+                    if (r < e) {
+                        if (ADJ)
+                            acc[r] = cmac_conj(acc[r], Tj[k + (int64_t)d * (o + r)], y);
+                        else
+                            acc[r] = cmac(acc[r], Tj[(o + r) + (int64_t)d * k], y);
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kBmax; ++r)
+                if (r < e) tile[t0 + r * lsj] = csub(tile[t0 + r * lsj], acc[r]);
+        }
+        __syncthreads();
+    }
+
+    // 3. local hyperplanes
+    for (int step = 0; step < sd.nll; ++step) {
+        const int lv = ADJ ? step : sd.nll - 1 - step;
+        const int i0 = lloff[lv], i1 = lloff[lv + 1];
+        for (int idx = i0 + threadIdx.x; idx < i1; idx += blockDim.x) {
+            const int t = llist[idx];
+            const uint64_t c = code[t];
+            if (ts.ragged && !entry_valid(c, sd, ts)) continue;
+            double2 num = tile[t];
+            double2 den = ts.shift;
+            for (int j = 0; j < sd.M; ++j) {
+                const int w = sd.bitw[j];
+                const int loc = w ? (int)((c >> sd.bitoff[j]) & ((1ull << w) - 1ull)) : 0;
+                const int b = sd.b[j], lsj = sd.ls[j];
+                const double2 *Td = tdiag + sd.tdoff[j];
+                const double2 lam = Td[loc + b * loc];
+                den = cadd(den, ADJ ? cconj(lam) : lam);
+                if (ADJ) {
+                    for (int q = 1; q <= loc; ++q)
+                        num = csub(num, cmul(cconj(Td[(loc - q) + b * loc]), tile[t - q * lsj]));
+                } else {
+                    const int qmax = ts.e[j] - 1 - loc;
+                    for (int q = 1; q <= qmax; ++q)
+                        num = csub(num, cmul(Td[loc + b * (loc + q)], tile[t + q * lsj]));
+                }
+            }
+            tile[t] = cdiv(num, den);
+        }
+        __syncthreads();
+    }
+
+    // 4. write back
+    for (int t = threadIdx.x; t < sd.S; t += blockDim.x) {
+        if (ts.ragged && !entry_valid(code[t], sd, ts)) continue;
+        X[ts.base + goff[t]] = from_d2<V>(tile[t]);
+    }
+}
+
+template <typename V, bool ADJ>
+hipError_t run_sweep(const sylt_plan_s &p, V *X, hipStream_t s)
+{
+    const SweepPlan &sp = p.sweep;
+    auto ker = sweep_tile_kernel<V, ADJ>;
+    if (sp.lds_bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)ker,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)sp.lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    const int nlev = (int)sp.level_off.size() - 1;
+    for (int step = 0; step < nlev; ++step) {
+        const int lv = ADJ ? step : nlev - 1 - step;
+        const int64_t b0 = sp.level_off[lv], b1 = sp.level_off[lv + 1];
+        if (b1 <= b0) continue;
+        hipLaunchKernelGGL(ker, dim3((unsigned)(b1 - b0)), dim3(kThreads), sp.lds_bytes, s, X,
+                           p.dT, sp.desc, sp.d_tiles + b0, sp.d_goff, sp.d_code, sp.d_llist,
+                           sp.d_lloff);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int sweep_max_partial_block() { return kBmax; }
+
+hipError_t launch_sweep(const sylt_plan_s &p, int op, int precision, void *X, hipStream_t s)
+{
+    if (precision == SYLT_FP64) {
+        return op == SYLT_OP_N ? run_sweep<double2, false>(p, static_cast<double2 *>(X), s)
+                               : run_sweep<double2, true>(p, static_cast<double2 *>(X), s);
+    }
+    return op == SYLT_OP_N ? run_sweep<float2, false>(p, static_cast<float2 *>(X), s)
+                           : run_sweep<float2, true>(p, static_cast<float2 *>(X), s);
+}
+
+}  // namespace sylt

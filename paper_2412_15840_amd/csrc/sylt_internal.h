@@ -1,0 +1,197 @@
+// Internal declarations of libsylt (gfx950): complex arithmetic helpers, the
+// plan object and the launch helpers each kernel file exports to the API layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sylt.h"
+
+namespace sylt {
+
+constexpr int kMaxModes = 32;     // N limit of the ABI
+constexpr int kMaxExtent = 64;    // n_k limit of the ABI
+constexpr int kMaxGroup = 24;     // modes fused in one transform pass (n >= 2 each)
+
+// ----------------------------------------------------------------- complex
+// double2 / float2 hold (re, im).  All products are written as explicit fused
+// multiply-adds so the rounding is the same in every kernel.
+__host__ __device__ inline double2 cd(double re, double im) { return make_double2(re, im); }
+
+template <typename V> struct CTraits;
+template <> struct CTraits<double2> { using R = double; };
+template <> struct CTraits<float2> { using R = float; };
+
+// acc + a * b
+template <typename V>
+__device__ __forceinline__ V cmac(V acc, V a, V b)
+{
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+// acc + conj(a) * b
+template <typename V>
+__device__ __forceinline__ V cmac_conj(V acc, V a, V b)
+{
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__host__ __device__ inline double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
+__host__ __device__ inline double cabs2(double2 a) { return hypot(a.x, a.y); }
+__host__ __device__ inline double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// a / b by Smith's algorithm (R. L. Smith, CACM 5(8), 1962): scale by the
+// larger component of b to avoid overflow in |b|^2.
+__host__ __device__ inline double2 cdiv(double2 a, double2 b)
+{
+    if (fabs(b.x) >= fabs(b.y)) {
+        const double r = b.y / b.x;
+        const double den = b.x + b.y * r;
+        return make_double2((a.x + a.y * r) / den, (a.y - a.x * r) / den);
+    }
+    const double r = b.x / b.y;
+    const double den = b.x * r + b.y;
+    return make_double2((a.x * r + a.y) / den, (a.y * r - a.x) / den);
+}
+
+// principal square root: for z = x + iy with t = sqrt((|z| + |x|)/2),
+// sqrt(z) = (t, y/(2t)) when x >= 0 and (|y|/(2t), sign(y) t) otherwise.
+__host__ __device__ inline double2 csqrt_(double2 z)
+{
+    if (z.x == 0.0 && z.y == 0.0) return make_double2(0.0, 0.0);
+    const double t = sqrt(0.5 * (hypot(z.x, z.y) + fabs(z.x)));
+    if (z.x >= 0.0) return make_double2(t, z.y / (2.0 * t));
+    return make_double2(fabs(z.y) / (2.0 * t), copysign(t, z.y));
+}
+
+template <typename V> __device__ __forceinline__ double2 to_d2(V v);
+template <> __device__ __forceinline__ double2 to_d2<double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ double2 to_d2<float2>(float2 v) { return make_double2(v.x, v.y); }
+template <typename V> __device__ __forceinline__ V from_d2(double2 v);
+template <> __device__ __forceinline__ double2 from_d2<double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ float2 from_d2<float2>(double2 v)
+{
+    return make_float2((float)v.x, (float)v.y);
+}
+
+// ------------------------------------------------------ transform passes
+// A pass applies the mode products of a run of consecutive (non-singleton)
+// modes [a, b) to the tensor viewed as (Lin, G, Rout): Lin = product of the
+// extents below a, G = product of the group's extents, Rout = the rest.  One
+// workgroup owns a tile of lb x G x rb entries held in LDS.
+struct PassDesc {
+    int64_t Lin, G, Rout;
+    int lb, lbshift, rb;
+    int64_t ntl, ntr;       // tile counts along l and r
+    int ng;                 // modes in the group
+    int gd[kMaxGroup];      // extents
+    int gs[kMaxGroup];      // in-group strides
+    int64_t moff[kMaxGroup];  // offset of each member's matrix in the plan buffers
+    int uniform_n;          // common extent if all equal (else 0)
+    int maxn;               // largest extent in the group
+    size_t lds_bytes(size_t elem) const { return (size_t)lb * (size_t)G * (size_t)rb * elem; }
+};
+
+// ------------------------------------------------------------------ sweep
+struct SweepDesc {
+    int M;                       // compressed modes
+    int d[kMaxModes];
+    int64_t s[kMaxModes];        // global strides
+    int b[kMaxModes], nb[kMaxModes];
+    int ls[kMaxModes];           // local strides in the full tile
+    int bitoff[kMaxModes], bitw[kMaxModes];
+    int tdoff[kMaxModes];        // offsets of diagonal blocks in LDS (entries)
+    int64_t moff[kMaxModes];     // offsets of T_j in the plan's matrix buffer
+    int S;                       // entries of a full tile
+    int nll;                     // local levels
+    int tdiag;                   // total entries of the diagonal blocks
+    int nsing;                   // singleton modes: their scalars join every eigenvalue sum
+    int64_t singoff[kMaxModes];  // offsets of those 1x1 T_k in the matrix buffer
+};
+
+struct SweepPlan {
+    SweepDesc desc{};
+    std::vector<int64_t> level_off;  // tile-level offsets into tiles (size nlev + 1)
+    int *d_tiles = nullptr;          // tile ids sorted by tile level
+    int64_t *d_goff = nullptr;       // global offset of each local entry
+    uint64_t *d_code = nullptr;      // packed local coordinates
+    int *d_llist = nullptr;          // local entries sorted by local level
+    int *d_lloff = nullptr;          // local level offsets
+    size_t lds_bytes = 0;
+};
+
+}  // namespace sylt
+
+// ------------------------------------------------------------------- plan
+struct sylt_plan_s {
+    int device = 0;
+    int N = 0;
+    std::vector<int64_t> n;          // extents as given
+    int64_t ntot = 0;
+    // compressed view: the modes with n_k > 1
+    int M = 0;
+    std::vector<int> cmode;          // compressed -> original mode
+    std::vector<int> cdim;
+    std::vector<int64_t> cstride;
+    // per original mode: offset (in complex entries) of its n_k x n_k matrix
+    std::vector<int64_t> moff;
+    int64_t mtotal = 0;
+    bool has_A = false;
+    // device buffers (complex128 unless noted)
+    double2 *dA = nullptr;           // A_k
+    double2 *dU = nullptr;           // U_k
+    double2 *dUh = nullptr;          // U_k^* (conjugate transpose), column-major
+    double2 *dT = nullptr;           // T_k
+    float2 *dU32 = nullptr;          // complex64 copies
+    float2 *dUh32 = nullptr;
+    int *dStatus = nullptr;          // per-mode Schur status
+    double *dScratch = nullptr;      // small reduction scratch (plan-owned)
+    size_t scratch_bytes = 0;
+    double sep = 0.0;
+    std::vector<sylt::PassDesc> passes;   // transform passes (one LDS tile)
+    std::vector<sylt::PassDesc> rpasses;  // residual passes (two LDS tiles)
+    sylt::SweepPlan sweep;
+};
+
+namespace sylt {
+
+// launch helpers implemented in the kernel files -----------------------------
+hipError_t launch_schur(const sylt_plan_s &p, int max_iter_per_n, hipStream_t s);
+hipError_t launch_prepare_factors(const sylt_plan_s &p, hipStream_t s);
+hipError_t launch_separation(const sylt_plan_s &p, double *d_out, hipStream_t s);
+hipError_t launch_transform(const sylt_plan_s &p, int dir, int precision, void *X, hipStream_t s);
+hipError_t launch_sweep(const sylt_plan_s &p, int op, int precision, void *X, hipStream_t s);
+// R64 (complex128, may alias B) = B - sum_k A_k x_k X; if R32 != nullptr the
+// final pass also stores R as complex64.  Partial sums of |R|^2 and |B|^2 are
+// reduced into norms2_dev[0..1] (device).
+hipError_t launch_residual(const sylt_plan_s &p, const double2 *B, const double2 *X, double2 *R64,
+                           float2 *R32, double *norms2_dev, hipStream_t s);
+hipError_t launch_axpy_c64(double2 *X, const float2 *D, int64_t n, int assign, hipStream_t s);
+hipError_t launch_convert_c128_c64(float2 *out, const double2 *in, int64_t n, hipStream_t s);
+hipError_t launch_copy_c128(double2 *out, const double2 *in, int64_t n, hipStream_t s);
+hipError_t launch_grad_A(const sylt_plan_s &p, const double2 *G, const double2 *X, double2 *const *GA,
+                         void *ws, size_t ws_bytes, hipStream_t s);
+size_t grad_A_workspace(const sylt_plan_s &p);
+
+// planning (api.cpp)
+void plan_passes(sylt_plan_s &p);
+int plan_sweep(sylt_plan_s &p);
+size_t max_lds_bytes();
+
+}  // namespace sylt

@@ -16,7 +16,7 @@ namespace {
 constexpr int kSchurIterPerN = 30;
 constexpr int64_t kTransformTileCap = 8192;  // complex entries per transform tile
 constexpr int64_t kResidualTileCap = 5120;   // two tiles (X and accumulator), 160 KB
-constexpr int64_t kSweepTileCap = 8192;
+constexpr int64_t kSweepTileCap = 9728;      // entries; with the diagonal blocks <= 160 KB
 
 int status_of(hipError_t e)
 {
@@ -283,6 +283,30 @@ int plan_sweep(sylt_plan_s &p)
     {
         std::vector<int64_t> fill(sp.level_off.begin(), sp.level_off.end() - 1);
         for (int64_t id = 0; id < ntiles; ++id) tiles[fill[tlev[id]]++] = (int)id;
+    }
+    // within a level, Z-order (bit-interleaved block indices): consecutive
+    // tiles are neighbours in every mode, so they share pull sources
+    {
+        int maxnb = 1;
+        for (int j = 0; j < M; ++j) maxnb = std::max(maxnb, sd.nb[j]);
+        const int bits = std::max(1, ilog2(maxnb));
+        if (M * bits <= 64) {  // otherwise keep the id order
+            std::vector<uint64_t> key(ntiles);
+            for (int64_t id = 0; id < ntiles; ++id) {
+                int64_t rem = id;
+                uint64_t k = 0;
+                for (int j = 0; j < M; ++j) {
+                    const uint64_t P = (uint64_t)(rem % sd.nb[j]);
+                    rem /= sd.nb[j];
+                    for (int bit = 0; bit < bits; ++bit)
+                        k |= ((P >> bit) & 1ull) << (bit * M + j);
+                }
+                key[id] = k;
+            }
+            for (int l = 0; l < nlev; ++l)
+                std::sort(tiles.begin() + sp.level_off[l], tiles.begin() + sp.level_off[l + 1],
+                          [&](int a, int b) { return key[a] < key[b]; });
+        }
     }
     SYLT_TRY(hipMalloc(&sp.d_goff, S * sizeof(int64_t)));
     SYLT_TRY(hipMalloc(&sp.d_code, S * sizeof(uint64_t)));

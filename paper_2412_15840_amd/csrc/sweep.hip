@@ -27,8 +27,20 @@
 namespace sylt {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 1024;
 constexpr int kBmax = 8;   // largest block of a partially tiled mode
+constexpr int kPrefetch = 8;  // pulled entries loaded before they are used
+constexpr int kXcds = 8;   // workgroups are dealt to the XCDs round-robin
+
+// Tiles of a level are stored in Z-order; give each XCD one contiguous chunk
+// of that order (workgroup b runs on XCD b % 8), so tiles that share pull
+// sources run on the same L2.
+__device__ __forceinline__ int tile_slot(int b, int nt)
+{
+    const int x = b % kXcds, slot = b / kXcds;
+    const int full = nt / kXcds, rem = nt % kXcds;
+    return x * full + min(x, rem) + slot;
+}
 
 struct TileState {
     int o[kMaxModes];
@@ -62,7 +74,7 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
     __shared__ TileState ts;
 
     if (threadIdx.x == 0) {
-        int rem = tiles[blockIdx.x];
+        int rem = tiles[tile_slot(blockIdx.x, gridDim.x)];
         int64_t base = 0;
         int ragged = 0;
         for (int j = 0; j < sd.M; ++j) {
@@ -116,15 +128,24 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
             double2 acc[kBmax];
 #pragma unroll
             for (int r = 0; r < kBmax; ++r) acc[r] = make_double2(0.0, 0.0);
-            for (int k = k0; k < k1; ++k) {
-                const double2 y = to_d2<V>(X[g0 + (int64_t)(k - o) * sj]);
+            for (int kb = k0; kb < k1; kb += kPrefetch) {
+                double2 y[kPrefetch];
 #pragma unroll
-                for (int r = 0; r < kBmax; ++r) {
-                    if (r < e) {
-                        if (ADJ)
-                            acc[r] = cmac_conj(acc[r], Tj[k + (int64_t)d * (o + r)], y);
-                        else
-                            acc[r] = cmac(acc[r], Tj[(o + r) + (int64_t)d * k], y);
+                for (int u = 0; u < kPrefetch; ++u)
+                    y[u] = kb + u < k1 ? to_d2<V>(X[g0 + (int64_t)(kb + u - o) * sj])
+                                       : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int u = 0; u < kPrefetch; ++u) {
+                    const int k = kb + u;
+                    if (k >= k1) break;  // uniform
+#pragma unroll
+                    for (int r = 0; r < kBmax; ++r) {
+                        if (r < e) {
+                            if (ADJ)
+                                acc[r] = cmac_conj(acc[r], Tj[k + (int64_t)d * (o + r)], y[u]);
+                            else
+                                acc[r] = cmac(acc[r], Tj[(o + r) + (int64_t)d * k], y[u]);
+                        }
                     }
                 }
             }

@@ -201,6 +201,332 @@ __global__ void __launch_bounds__(kThreads) transform_pass_kernel(V *__restrict_
     store_tile<V>(X, tile, pa, tc);
 }
 
+// ------------------------------------------------ pipelined uniform pass
+// Persistent workgroups of 512 lanes walk the tiles; while the products of
+// tile t run in LDS, the loads of tile t + grid are already in flight into
+// registers.  Each fibre's NN outputs are split into P wave-uniform parts of
+// NP rows, so every wave has work even when a tile holds few fibres; a round
+// covers 512 / P whole fibres: all parts read their inputs, a barrier, then
+// all write (the fibre is updated in place).
+constexpr int kPipeThreads = 512;
+constexpr int kPipeRegs = 16;  // tile entries per lane (tiles <= 8192 entries)
+
+template <typename V, int NN, int NP, int PART>
+__device__ __forceinline__ void fibre_part(const V *tile, int base, int stride,
+                                           const V *__restrict__ M, V (&y)[NP])
+{
+    constexpr int I0 = PART * NP;
+    constexpr int CNT = NN - I0 < NP ? (NN - I0 > 0 ? NN - I0 : 0) : NP;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) y[i] = vzero<V>();
+    // the column loop stays rolled: each iteration needs only its CNT matrix
+    // entries in scalar registers, and the next input is already in flight
+    V xn = tile[base];
+#pragma unroll 1
+    for (int m = 0; m < NN; ++m) {
+        const V x = xn;
+        if (m + 1 < NN) xn = tile[base + (m + 1) * stride];
+        const V *Mm = M + I0 + NN * m;
+#pragma unroll
+        for (int i = 0; i < CNT; ++i) y[i] = cmac(y[i], Mm[i], x);
+    }
+}
+
+template <typename V>
+__device__ __forceinline__ int64_t elem_addr(const PassDesc &pa, const TileCoord &tc, int e,
+                                             bool &valid)
+{
+    const int l = e & (pa.lb - 1);
+    const int rest = e >> pa.lbshift;
+    const int g = rest % (int)pa.G, r = rest / (int)pa.G;
+    valid = l < tc.lbe && r < tc.rbe;
+    return tc.l0 + l + pa.Lin * (g + pa.G * (tc.r0 + r));
+}
+
+__device__ __forceinline__ TileCoord tile_coord_of(const PassDesc &pa, int64_t t)
+{
+    TileCoord c;
+    const int64_t tl = t % pa.ntl, tr = t / pa.ntl;
+    c.l0 = tl * pa.lb;
+    c.r0 = tr * pa.rb;
+    c.lbe = (int)min((int64_t)pa.lb, pa.Lin - c.l0);
+    c.rbe = (int)min((int64_t)pa.rb, pa.Rout - c.r0);
+    return c;
+}
+
+template <typename V, int NN, int P>
+__global__ void __launch_bounds__(kPipeThreads) transform_pipe_kernel(V *__restrict__ X,
+                                                                      const V *__restrict__ Mbuf,
+                                                                      PassDesc pa)
+{
+    constexpr int FR = kPipeThreads / P;  // fibres per round (multiple of 64)
+    constexpr int NP = (NN + P - 1) / P;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V *tile = reinterpret_cast<V *>(smem_raw);
+    const int total = pa.lb * (int)pa.G * pa.rb;
+    const int64_t ntiles = pa.ntl * pa.ntr;
+    const int part = threadIdx.x / FR;  // wave-uniform
+    const int fl = threadIdx.x % FR;
+
+    using R = typename CTraits<V>::R;
+    R pre_re[kPipeRegs], pre_im[kPipeRegs];
+    int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    // this lane's tile entries e = lane + i*512 -> (l, g, r); their offsets
+    // from the tile origin are the same for every tile of the pass
+    int64_t off[kPipeRegs];
+    int lr[kPipeRegs];  // l | r << 16, or -1 beyond the tile
+#pragma unroll
+    for (int i = 0; i < kPipeRegs; ++i) {
+        const int e = threadIdx.x + i * kPipeThreads;
+        const int l = e & (pa.lb - 1);
+        const int rest = e >> pa.lbshift;
+        const int g = rest % (int)pa.G, r = rest / (int)pa.G;
+        off[i] = l + pa.Lin * (g + pa.G * r);
+        lr[i] = e < total ? (l | (r << 16)) : -1;
+    }
+    auto load_regs = [&](const TileCoord &c) {
+        const int64_t org = c.l0 + pa.Lin * pa.G * c.r0;
+        const bool whole = c.lbe == pa.lb && c.rbe == pa.rb;
+#pragma unroll
+        for (int i = 0; i < kPipeRegs; ++i) {
+            const bool ok = lr[i] >= 0 &&
+                            (whole || ((lr[i] & 0xffff) < c.lbe && (lr[i] >> 16) < c.rbe));
+            if (ok) {
+                const V v = X[org + off[i]];
+                pre_re[i] = v.x;
+                pre_im[i] = v.y;
+            }
+        }
+    };
+    TileCoord tc = tile_coord_of(pa, t);
+    load_regs(tc);
+    while (true) {
+        // registers -> LDS (the tile of this iteration)
+#pragma unroll
+        for (int i = 0; i < kPipeRegs; ++i) {
+            const int e = threadIdx.x + i * kPipeThreads;
+            if (e < total) {
+                tile[e].x = pre_re[i];
+                tile[e].y = pre_im[i];
+            }
+        }
+        __syncthreads();
+        const int64_t tn = t + gridDim.x;
+        const TileCoord tcn = tile_coord_of(pa, tn < ntiles ? tn : t);
+        if (tn < ntiles) load_regs(tcn);
+        for (int q = 0; q < pa.ng; ++q) {
+            const int nfib = pa.lb * (int)(pa.G / NN) * tc.rbe;
+            const int stride = pa.lb * pa.gs[q];
+            const V *M = Mbuf + pa.moff[q];
+            for (int f0 = 0; f0 < nfib; f0 += FR) {
+                const int f = f0 + fl;
+                const int base = f < nfib ? fibre_base(pa, tc, q, NN, f) : -1;
+                V y[NP];
+                if (base >= 0) {
+                    switch (part) {
+#define SYLT_PART(K) \
+    case K: if constexpr (K < P) fibre_part<V, NN, NP, K>(tile, base, stride, M, y); break;
+                        SYLT_PART(0) SYLT_PART(1) SYLT_PART(2) SYLT_PART(3)
+                        SYLT_PART(4) SYLT_PART(5) SYLT_PART(6) SYLT_PART(7)
+#undef SYLT_PART
+                        default: break;
+                    }
+                }
+                __syncthreads();
+                if (base >= 0) {
+#pragma unroll
+                    for (int i = 0; i < NP; ++i)
+                        if (part * NP + i < NN) tile[base + (part * NP + i) * stride] = y[i];
+                }
+                __syncthreads();
+            }
+        }
+        // LDS -> global
+        {
+            const int64_t org = tc.l0 + pa.Lin * pa.G * tc.r0;
+            const bool whole = tc.lbe == pa.lb && tc.rbe == pa.rb;
+#pragma unroll
+            for (int i = 0; i < kPipeRegs; ++i) {
+                const bool ok = lr[i] >= 0 &&
+                                (whole || ((lr[i] & 0xffff) < tc.lbe && (lr[i] >> 16) < tc.rbe));
+                if (ok) X[org + off[i]] = tile[threadIdx.x + i * kPipeThreads];
+            }
+        }
+        if (tn >= ntiles) break;
+        __syncthreads();
+        t = tn;
+        tc = tcn;
+    }
+}
+
+// ------------------------------------------------------ MFMA pass
+// The product of one mode is a dense complex GEMM Y = M X over the fibres of
+// the tile.  With re/im interleaved along rows and columns it becomes a real
+// GEMM with the 2n x 2n matrix R[2i+a][2m+b] = {Re M, -Im M; Im M, Re M}
+// (a, b in {0, 1}), zero-padded to 16-row blocks and 4-column steps, run on
+// the 16x16x4 matrix cores: R lives in A fragments, 16 fibres of a wave are
+// the B operand (each lane reads one real component straight from LDS) and
+// the 16x16 result blocks are written back in place.  Lane layouts of
+// v_mfma_{f64,f32}_16x16x4: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
+// result D[i][j] in lane j + 16*(i/4) value i%4 (f32) and in lane j + 16*(i%4)
+// value i/4 (f64).
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+template <typename R> struct MfmaT;
+template <> struct MfmaT<double> {
+    using acc = mf_d4;
+    static __device__ __forceinline__ acc mma(double a, double b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // row of the 16-row block held by value v of lane l
+    static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+template <> struct MfmaT<float> {
+    using acc = mf_f4;
+    static __device__ __forceinline__ acc mma(float a, float b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+// two waves per SIMD; each lane prefetches 16 entries of the next tile
+constexpr int kMfmaThreads = 512;
+constexpr int kMfmaRegs = 16;  // tile entries per lane (tiles <= 8192 entries)
+
+template <typename V, int NN>
+__global__ void __launch_bounds__(kMfmaThreads) transform_mfma_kernel(V *__restrict__ X,
+                                                                      const V *__restrict__ Mbuf,
+                                                                      PassDesc pa)
+{
+    using R = typename CTraits<V>::R;
+    using MT = MfmaT<R>;
+    constexpr int RB = (2 * NN + 15) / 16;  // 16-row blocks of the real matrix
+    constexpr int KS = (2 * NN + 3) / 4;    // 4-column steps
+    constexpr int WAVES = kMfmaThreads / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V *tile = reinterpret_cast<V *>(smem_raw);
+    const int total = pa.lb * (int)pa.G * pa.rb;
+    const int64_t ntiles = pa.ntl * pa.ntr;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // A fragments of every mode of the pass, in fragment order, after the tile
+    R *afr = reinterpret_cast<R *>(tile + total);
+    for (int idx = threadIdx.x; idx < pa.ng * RB * KS * 64; idx += kMfmaThreads) {
+        const int l = idx & 63;
+        const int frag = idx >> 6;
+        const int kk = frag % KS, rb = (frag / KS) % RB, q = frag / (KS * RB);
+        const int row = 16 * rb + (l & 15), k = 4 * kk + (l >> 4);
+        const int i = row >> 1, m = k >> 1;
+        R v = 0;
+        if (i < NN && m < NN) {
+            const V c = Mbuf[pa.moff[q] + i + NN * m];
+            const int a = row & 1, b = k & 1;
+            v = a == b ? c.x : (a ? c.y : -c.y);
+        }
+        afr[idx] = v;
+    }
+
+    R pre_re[kMfmaRegs], pre_im[kMfmaRegs];
+    int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    // address of tile entry e (rb == 1 needs no division)
+    auto entry_addr = [&](const TileCoord &c, int e, bool &ok) -> int64_t {
+        const int l = e & (pa.lb - 1);
+        const int rest = e >> pa.lbshift;
+        int g = rest, r = 0;
+        if (pa.rb > 1) {
+            g = rest % (int)pa.G;
+            r = rest / (int)pa.G;
+        }
+        ok = e < total && l < c.lbe && r < c.rbe;
+        return c.l0 + l + pa.Lin * (g + pa.G * (c.r0 + r));
+    };
+    auto load_regs = [&](const TileCoord &c) {
+#pragma unroll
+        for (int i = 0; i < kMfmaRegs; ++i) {
+            bool ok;
+            const int64_t a = entry_addr(c, threadIdx.x + i * kMfmaThreads, ok);
+            if (ok) {
+                const V v = X[a];
+                pre_re[i] = v.x;
+                pre_im[i] = v.y;
+            }
+        }
+    };
+    TileCoord tc = tile_coord_of(pa, t);
+    load_regs(tc);
+    while (true) {
+#pragma unroll
+        for (int i = 0; i < kMfmaRegs; ++i) {
+            const int e = threadIdx.x + i * kMfmaThreads;
+            if (e < total) {
+                tile[e].x = pre_re[i];
+                tile[e].y = pre_im[i];
+            }
+        }
+        __syncthreads();
+        const int64_t tn = t + gridDim.x;
+        const TileCoord tcn = tile_coord_of(pa, tn < ntiles ? tn : t);
+        if (tn < ntiles) load_regs(tcn);
+        for (int q = 0; q < pa.ng; ++q) {
+            const R *aq = afr + q * RB * KS * 64 + lane;
+            const int nfib = pa.lb * (int)(pa.G / NN) * tc.rbe;
+            const int stride = pa.lb * pa.gs[q];
+            const int ngroups = (nfib + 15) >> 4;
+            // B operand of a group of 16 fibres: each lane reads one real value
+            // per k-step; the k-step loop stays rolled (by two) so only a few
+            // operands are live, and the RB accumulator chains interleave
+            const R *tr = reinterpret_cast<const R *>(tile);
+            for (int grp = wave; grp < ngroups; grp += WAVES) {
+                const int f = 16 * grp + (lane & 15);
+                const int base = f < nfib ? fibre_base(pa, tc, q, NN, f) : -1;
+                const int kb = lane >> 4;  // k within a step
+                typename MT::acc acc[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) acc[rb] = typename MT::acc{0, 0, 0, 0};
+#pragma unroll 2
+                for (int kk = 0; kk < KS; ++kk) {
+                    const int k = 4 * kk + kb;
+                    const int m = k >> 1;
+                    const R b = (base >= 0 && m < NN) ? tr[2 * (base + m * stride) + (k & 1)] : R(0);
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+                        acc[rb] = MT::mma(aq[(rb * KS + kk) * 64], b, acc[rb]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                if (base >= 0) {
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int row = 16 * rb + MT::row(lane, v);
+                            const int i = row >> 1;
+                            if (i < NN) {
+                                R *dst = reinterpret_cast<R *>(&tile[base + i * stride]);
+                                dst[row & 1] = acc[rb][v];
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < kMfmaRegs; ++i) {
+            const int e = threadIdx.x + i * kMfmaThreads;
+            bool ok;
+            const int64_t a = entry_addr(tc, e, ok);
+            if (ok) X[a] = tile[e];
+        }
+        if (tn >= ntiles) break;
+        __syncthreads();
+        t = tn;
+        tc = tcn;
+    }
+}
+
 // extents up to 64: ping-pong between two LDS tiles
 template <typename V>
 __global__ void __launch_bounds__(kThreads) transform_pass_generic_kernel(
@@ -357,7 +683,68 @@ hipError_t run_transform_pass(const PassDesc &pa, V *X, const V *Mbuf, hipStream
         if (e != hipSuccess) return e;                                                    \
         hipLaunchKernelGGL(KER, dim3((unsigned)tiles), dim3(kThreads), lds, s, X, Mbuf, pa); \
     } while (0)
-    if (generic) {
+    const bool pipe = !generic && pa.lb * pa.G * pa.rb <= kPipeRegs * kPipeThreads &&
+                      (pa.uniform_n == 2 || pa.uniform_n == 4 || pa.uniform_n == 8 ||
+                       pa.uniform_n == 16 || pa.uniform_n == 19);
+    if (pipe) {
+        static int cus = 0;
+        if (!cus) {
+            int dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+                cus = 256;
+        }
+#define SYLT_PIPE(NNV, PV)                                                                     \
+    do {                                                                                       \
+        auto ker = transform_pipe_kernel<V, NNV, PV>;                                          \
+        e = allow_lds(ker, lds);                                                               \
+        if (e != hipSuccess) return e;                                                         \
+        int occ = 1;                                                                           \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ker, kPipeThreads, lds) !=      \
+                hipSuccess || occ < 1)                                                         \
+            occ = 1;                                                                           \
+        const int64_t grid = std::min<int64_t>(tiles, (int64_t)cus * occ);                     \
+        hipLaunchKernelGGL(ker, dim3((unsigned)grid), dim3(kPipeThreads), lds, s, X, Mbuf, pa); \
+    } while (0)
+        static int max_lds = 0;
+        if (!max_lds) {
+            int dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                    hipSuccess)
+                max_lds = 65536;
+        }
+        // the MFMA variant also keeps the real-form matrix fragments in LDS;
+        // if they do not fit next to the tile, the VALU variant runs instead
+#define SYLT_MFMA(NNV, PV)                                                                      \
+    do {                                                                                        \
+        constexpr int RBv = (2 * NNV + 15) / 16, KSv = (2 * NNV + 3) / 4;                       \
+        const size_t ldsm =                                                                     \
+            lds + (size_t)pa.ng * RBv * KSv * 64 * sizeof(typename CTraits<V>::R);             \
+        if (ldsm > (size_t)max_lds) {                                                           \
+            SYLT_PIPE(NNV, PV);                                                                 \
+            break;                                                                              \
+        }                                                                                       \
+        auto ker = transform_mfma_kernel<V, NNV>;                                               \
+        e = allow_lds(ker, ldsm);                                                               \
+        if (e != hipSuccess) return e;                                                          \
+        int occ = 1;                                                                            \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ker, kMfmaThreads, ldsm) !=      \
+                hipSuccess || occ < 1)                                                          \
+            occ = 1;                                                                            \
+        const int64_t grid = std::min<int64_t>(tiles, (int64_t)cus * occ);                      \
+        hipLaunchKernelGGL(ker, dim3((unsigned)grid), dim3(kMfmaThreads), ldsm, s, X, Mbuf, pa); \
+    } while (0)
+        switch (pa.uniform_n) {
+            case 2: SYLT_PIPE(2, 1); break;
+            case 4: SYLT_PIPE(4, 1); break;
+            case 8: SYLT_MFMA(8, 2); break;
+            case 16: SYLT_MFMA(16, 4); break;
+            default: SYLT_MFMA(19, 4); break;
+        }
+#undef SYLT_PIPE
+#undef SYLT_MFMA
+    } else if (generic) {
         SYLT_LAUNCH(transform_pass_generic_kernel<V>);
     } else {
         switch (pa.uniform_n) {

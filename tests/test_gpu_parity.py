@@ -39,6 +39,8 @@ SHAPES = [
     (5, 3, 7, 1, 9),              # ragged tiles in every mode
     (2,) * 12,                    # n = 2 regime
     (19, 19, 19),                 # n = 19 regime, ragged blocks
+    (16, 16, 16),                 # n = 16 (matrix-core transform, no padding)
+    (19, 19, 19, 19),             # two fused passes, the second with ragged tiles
     (33, 5),                      # extent > 24: generic transform path
     (64, 3),                      # the largest supported extent
     (11,),                        # N = 1: a plain triangular solve

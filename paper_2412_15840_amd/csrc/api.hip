@@ -16,7 +16,6 @@ namespace {
 constexpr int kSchurIterPerN = 30;
 constexpr int64_t kTransformTileCap = 8192;  // complex entries per transform tile
 constexpr int64_t kResidualTileCap = 5120;   // two tiles (X and accumulator), 160 KB
-constexpr int64_t kSweepTileCap = 9728;      // entries; with the diagonal blocks <= 160 KB
 
 int status_of(hipError_t e)
 {
@@ -308,6 +307,33 @@ int plan_sweep(sylt_plan_s &p)
                           [&](int a, int b) { return key[a] < key[b]; });
         }
     }
+    // per-lane packed local-solve work (one 32-bit word per lane and round)
+    std::vector<int> lanetab(1, -1);
+    sd.packed = 0;
+    sd.rounds = 0;
+    if (S <= (1 << 14) && bitpos <= 17) {
+        std::vector<int> roff(nll + 1, 0);
+        for (int l = 0; l < nll; ++l) {
+            const int w = lloff[l + 1] - lloff[l];
+            roff[l + 1] = roff[l] + (w + kSweepThreads - 1) / kSweepThreads;
+        }
+        if (roff[nll] <= kSweepMaxRounds) {
+            lanetab.assign((size_t)roff[nll] * kSweepThreads, -1);
+            for (int l = 0; l < nll; ++l)
+                for (int idx = lloff[l]; idx < lloff[l + 1]; ++idx) {
+                    const int k = idx - lloff[l];
+                    const int r = roff[l] + k / kSweepThreads, lane = k % kSweepThreads;
+                    const int t = llist[idx];
+                    lanetab[(size_t)r * kSweepThreads + lane] = t | (int)(code[t] << 14);
+                    sd.round_level[r] = l;
+                }
+            sd.packed = 1;
+            sd.rounds = roff[nll];
+        }
+    }
+    SYLT_TRY(hipMalloc(&sp.d_lanetab, lanetab.size() * sizeof(int)));
+    SYLT_TRY(hipMemcpy(sp.d_lanetab, lanetab.data(), lanetab.size() * sizeof(int),
+                       hipMemcpyHostToDevice));
     SYLT_TRY(hipMalloc(&sp.d_goff, S * sizeof(int64_t)));
     SYLT_TRY(hipMalloc(&sp.d_code, S * sizeof(uint64_t)));
     SYLT_TRY(hipMalloc(&sp.d_llist, S * sizeof(int)));
@@ -344,6 +370,7 @@ void free_plan(sylt_plan_s *p)
     hipFree(p->sweep.d_code);
     hipFree(p->sweep.d_llist);
     hipFree(p->sweep.d_lloff);
+    hipFree(p->sweep.d_lanetab);
     delete p;
 }
 

@@ -15,6 +15,9 @@ namespace sylt {
 constexpr int kMaxModes = 32;     // N limit of the ABI
 constexpr int kMaxExtent = 64;    // n_k limit of the ABI
 constexpr int kMaxGroup = 24;     // modes fused in one transform pass (n >= 2 each)
+constexpr int kSweepTileCap = 9728;   // sweep tile entries (with diagonal blocks <= 160 KB LDS)
+constexpr int kSweepThreads = 1024;   // lanes of a sweep workgroup
+constexpr int kSweepMaxRounds = 32;   // local-solve rounds held per lane in registers
 
 // ----------------------------------------------------------------- complex
 // double2 / float2 hold (re, im).  All products are written as explicit fused
@@ -121,6 +124,10 @@ struct SweepDesc {
     int S;                       // entries of a full tile
     int nll;                     // local levels
     int tdiag;                   // total entries of the diagonal blocks
+    int packed;                  // local-solve work in the per-lane packed table
+    int rounds;                  // rounds of that table (levels wider than the
+                                 // workgroup take several rounds)
+    int round_level[kSweepMaxRounds];  // local level of each round, ascending
     int nsing;                   // singleton modes: their scalars join every eigenvalue sum
     int64_t singoff[kMaxModes];  // offsets of those 1x1 T_k in the matrix buffer
 };
@@ -133,6 +140,7 @@ struct SweepPlan {
     uint64_t *d_code = nullptr;      // packed local coordinates
     int *d_llist = nullptr;          // local entries sorted by local level
     int *d_lloff = nullptr;          // local level offsets
+    int *d_lanetab = nullptr;        // [round][lane] packed local-solve work items
     size_t lds_bytes = 0;
 };
 

@@ -143,7 +143,9 @@ def test_solve_matches_oracle(name):
     assert torch.equal(X, X2)
 
 
-@pytest.mark.parametrize("n", [(7,), (1, 1, 1), (4, 1, 1, 6), (2, 3, 2, 3, 2, 3, 2)])
+@pytest.mark.parametrize("n", [(7,), (1, 1, 1), (4, 1, 1, 6), (2, 3, 2, 3, 2, 3, 2),
+                               (2,) * 16 + (1,) * 16,      # N = 32, the largest supported
+                               (64, 64, 2)])               # largest extent, two passes
 def test_solve_edge_shapes(n):
     sylt = _sylt()
     banner(f"solve edge {n}")

@@ -43,6 +43,59 @@ def parse():
     return ap.parse_args()
 
 
+def source_digest(relpath):
+    import hashlib
+    with open(os.path.join(ROOT, relpath), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` at `workload` from the committed
+    counter summary (profiles/kernel_traffic.txt: FETCH_SIZE and WRITE_SIZE,
+    each scaled by what the counter reads for a copy of known size).  None if
+    absent or if the kernel's source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "kernel_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = dict(kv.split("=", 1) for kv in line.split() if "=" in kv)
+        if f.get("kernel") != kernel or f.get("workload") != workload:
+            continue
+        if f.get("source_sha256") != source_digest(f.get("source", "")):
+            return None
+        return float(f["hbm_bytes_per_launch"])
+    return None
+
+
+def roofline_entry(kernel, flops, bytes_alg, ms_total, launches, matrix_core, workload, source):
+    """Roofline of one kernel over `launches` launches: the binding roof of its
+    algorithmic work (FP64 arithmetic or HBM), achieved = algorithmic work per
+    launch / average launch duration."""
+    t = ms_total * 1e-3
+    t_hbm = bytes_alg / (HBM_PEAK_GBS * 1e9)
+    t_fp = flops / (FP64_VECTOR_PEAK_TF * 1e12)
+    traffic = measured_traffic(kernel, workload)
+    if t_fp >= t_hbm:
+        ach = flops / t / 1e12
+        out = {"kernel": kernel, "bound": "mfma" if matrix_core else "alu",
+               "achieved": round(ach, 3), "peak": FP64_VECTOR_PEAK_TF, "unit": "TFLOP/s",
+               "frac": round(ach / FP64_VECTOR_PEAK_TF, 4)}
+    else:
+        ach = bytes_alg / t / 1e9
+        out = {"kernel": kernel, "bound": "hbm", "achieved": round(ach, 1),
+               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4)}
+    out["traffic"] = traffic
+    out["alg_bytes_per_launch"] = bytes_alg / launches
+    out["alg_flops_per_launch"] = flops / launches
+    out["avg_launch_ms"] = round(ms_total / launches, 4)
+    out["launches"] = launches
+    if traffic is not None:
+        out["traffic_over_alg_bytes"] = round(traffic / (bytes_alg / launches), 2)
+    return out
+
+
 def time_events(fn, reps, torch):
     """Average milliseconds per call of fn() on the current stream (HIP events)."""
     s = torch.cuda.current_stream()
@@ -180,17 +233,18 @@ def main():
             "avg_launch_ms": round(t_sw / n_lvl, 4),
             "tflops": sw_flops / (t_sw * 1e-3) / 1e12, "gbs_alg": sw_bytes / (t_sw * 1e-3) / 1e9},
     }
-    # dominant kernel = the one with the largest total time per solve
-    if 2 * t_tr >= t_sw:
-        ach = tr_flops / (t_tr * 1e-3) / 1e12
-        roof = {"kernel": "transform_pass_kernel<double2,19>", "bound": "alu",
-                "achieved": round(ach, 3), "peak": FP64_VECTOR_PEAK_TF, "unit": "TFLOP/s",
-                "frac": round(ach / FP64_VECTOR_PEAK_TF, 4), "traffic": None}
-    else:
-        ach = sw_bytes / (t_sw * 1e-3) / 1e9
-        roof = {"kernel": "sweep_tile_kernel<double2,false>", "bound": "hbm",
-                "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    # roofline of both hot kernels; the dominant one (largest time per solve)
+    # is the headline roofline object
+    tr_kernel = ("transform_mfma_kernel<double2,%d>" % n[0]
+                 if all(v == n[0] for v in n) else "transform_pass_kernel")
+    sw_kernel = "sweep_tile_kernel<double2,false,%d>" % len([v for v in n if v > 1])
+    roof_tr = roofline_entry(tr_kernel, tr_flops, tr_bytes * n_pass, t_tr, n_pass, True, w.name,
+                             "paper_2412_15840_amd/csrc/transform.hip")
+    roof_sw = roofline_entry(sw_kernel, sw_flops, sw_bytes, t_sw, n_lvl, False, w.name,
+                             "paper_2412_15840_amd/csrc/sweep.hip")
+    roof = roof_sw if t_sw >= 2 * t_tr else roof_tr
+    kernels["transform_pass"]["roofline"] = roof_tr
+    kernels["sweep_tile"]["roofline"] = roof_sw
     # whole-solve roofline: max(algorithmic bytes / HBM peak, flops / FP64 peak)
     t_hbm = (2 * tr_bytes + sw_bytes) / (HBM_PEAK_GBS * 1e9)
     t_fp = (2 * tr_flops + sw_flops) / (FP64_VECTOR_PEAK_TF * 1e12)

@@ -184,7 +184,7 @@ int plan_sweep(sylt_plan_s &p)
             S *= bb[j];
             td += (int64_t)bb[j] * bb[j];
         }
-        return std::pair<int64_t, size_t>(S, (size_t)(S + td) * sizeof(double2));
+        return std::pair<int64_t, size_t>(S, (size_t)(S + td + 1) * sizeof(double2));
     };
     // greedy: repeatedly take the move (a larger block on one mode) with the
     // best modelled gain that still fits the LDS budget
@@ -236,7 +236,8 @@ int plan_sweep(sylt_plan_s &p)
     sd.S = (int)S;
     sd.nll = nll;
     sd.tdiag = tdoff;
-    sp.lds_bytes = (size_t)(S + tdoff) * sizeof(double2);
+    sd.zero_slot = tdoff;  // one zero entry after the diagonal blocks
+    sp.lds_bytes = (size_t)(S + tdoff + 1) * sizeof(double2);
     if (sp.lds_bytes > lds_cap) return SYLT_E_UNSUPPORTED;
 
     // local tables of the full tile
@@ -331,6 +332,38 @@ int plan_sweep(sylt_plan_s &p)
             sd.rounds = roff[nll];
         }
     }
+    // pencil form of the local solve: one mode-0 pencil (loc_0 = 0 .. b_0-1)
+    // per lane, the waves grouped by the pencil's index sum over the other
+    // modes; it needs every group to fit the workgroup's waves
+    sd.penc = 0;
+    sd.pen_long = 0;
+    for (int j = 1; j < M; ++j) sd.pen_long |= b[j] > 3;
+    if (M >= 1 && M <= kSweepPencilModes && b[0] >= 4 && b[0] <= kSweepPencilMax && S <= (1 << 14) &&
+        bitpos <= 17) {
+        const int b0 = b[0];
+        const int np = (int)(S / b0);
+        std::vector<std::vector<int>> grp(nll - (b0 - 1));
+        for (int pcl = 0; pcl < np; ++pcl) {
+            const int64_t t0 = (int64_t)pcl * b0;
+            grp[lev[t0]].push_back((int)t0 | (int)(code[t0] << 14));
+        }
+        int waves = 0;
+        for (const auto &g : grp) waves += (int)((g.size() + 63) / 64);
+        if (waves <= kSweepThreads / 64) {
+            std::vector<int> tab(kSweepThreads, -1);
+            int w = 0;
+            for (const auto &g : grp)
+                for (size_t s0 = 0; s0 < g.size(); s0 += 64, ++w)
+                    for (size_t i = s0; i < std::min(g.size(), s0 + 64); ++i)
+                        tab[(size_t)w * 64 + (i - s0)] = g[i];
+            lanetab.swap(tab);
+            sd.penc = 1;
+            sd.packed = 0;
+            sd.rounds = 0;
+        }
+    }
+    SYLT_TRY(hipMalloc(&sp.d_desc, sizeof(SweepDesc)));
+    SYLT_TRY(hipMemcpy(sp.d_desc, &sd, sizeof(SweepDesc), hipMemcpyHostToDevice));
     SYLT_TRY(hipMalloc(&sp.d_lanetab, lanetab.size() * sizeof(int)));
     SYLT_TRY(hipMemcpy(sp.d_lanetab, lanetab.data(), lanetab.size() * sizeof(int),
                        hipMemcpyHostToDevice));
@@ -361,6 +394,7 @@ void free_plan(sylt_plan_s *p)
     hipFree(p->dU);
     hipFree(p->dUh);
     hipFree(p->dT);
+    hipFree(p->dTt);
     hipFree(p->dU32);
     hipFree(p->dUh32);
     hipFree(p->dStatus);
@@ -371,6 +405,7 @@ void free_plan(sylt_plan_s *p)
     hipFree(p->sweep.d_llist);
     hipFree(p->sweep.d_lloff);
     hipFree(p->sweep.d_lanetab);
+    hipFree(p->sweep.d_desc);
     delete p;
 }
 
@@ -401,6 +436,7 @@ int init_plan(sylt_plan_s *p, int N, const int64_t *n)
     SYLT_TRY(hipMalloc(&p->dU, mb));
     SYLT_TRY(hipMalloc(&p->dUh, mb));
     SYLT_TRY(hipMalloc(&p->dT, mb));
+    SYLT_TRY(hipMalloc(&p->dTt, p->mtotal * sizeof(double2)));
     SYLT_TRY(hipMalloc(&p->dU32, p->mtotal * sizeof(float2)));
     SYLT_TRY(hipMalloc(&p->dUh32, p->mtotal * sizeof(float2)));
     SYLT_TRY(hipMalloc(&p->dStatus, std::max(1, N) * sizeof(int)));
@@ -573,6 +609,7 @@ int sylt_plan_describe(sylt_plan p, char *buf, size_t len)
     s += "],\"tile_entries\":" + std::to_string(sd.S) +
          ",\"tiles\":" + std::to_string(p->sweep.level_off.empty() ? 0 : p->sweep.level_off.back()) +
          ",\"tile_levels\":" + std::to_string(launches) + ",\"local_levels\":" + std::to_string(sd.nll) +
+         ",\"local_solve\":\"" + (sd.penc ? "pencil" : sd.packed ? "packed" : "levels") + "\"" +
          ",\"lds_bytes\":" + std::to_string(p->sweep.lds_bytes) + "}}";
     const size_t n = std::min(len - 1, s.size());
     memcpy(buf, s.data(), n);

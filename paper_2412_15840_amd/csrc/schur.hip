@@ -220,7 +220,8 @@ struct PrepJobs {
 
 __global__ void prepare_factors_kernel(PrepJobs jobs, const double2 *__restrict__ U,
                                        double2 *__restrict__ Uh, float2 *__restrict__ U32,
-                                       float2 *__restrict__ Uh32)
+                                       float2 *__restrict__ Uh32, const double2 *__restrict__ T,
+                                       double2 *__restrict__ Tt)
 {
     const int job = blockIdx.x;
     const int n = jobs.n[job];
@@ -232,6 +233,7 @@ __global__ void prepare_factors_kernel(PrepJobs jobs, const double2 *__restrict_
         Uh[off + idx] = cconj(ut);
         U32[off + idx] = make_float2((float)u.x, (float)u.y);
         Uh32[off + idx] = make_float2((float)ut.x, (float)-ut.y);
+        Tt[off + idx] = T[off + j + (int64_t)n * i];
     }
 }
 
@@ -266,7 +268,7 @@ hipError_t launch_prepare_factors(const sylt_plan_s &p, hipStream_t s)
         ++jobs.count;
     }
     hipLaunchKernelGGL(prepare_factors_kernel, dim3(jobs.count), dim3(256), 0, s, jobs, p.dU,
-                       p.dUh, p.dU32, p.dUh32);
+                       p.dUh, p.dU32, p.dUh32, p.dT, p.dTt);
     return hipGetLastError();
 }
 

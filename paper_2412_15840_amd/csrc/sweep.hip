@@ -24,12 +24,17 @@
 // coefficients.
 #include "sylt_internal.h"
 
+#include <type_traits>
+
 namespace sylt {
 namespace {
 
 constexpr int kThreads = kSweepThreads;
 constexpr int kBmax = 8;   // largest block of a partially tiled mode
 constexpr int kPrefetch = 8;  // pulled entries loaded before they are used
+constexpr int kPen = kSweepPencilMax;  // pencil entries held in registers
+constexpr int kChunk0 = 4;    // mode-0 coefficients loaded together
+static_assert(kPen % kChunk0 == 0, "pencil length must be whole chunks");
 constexpr int kXcds = 8;   // workgroups are dealt to the XCDs round-robin
 constexpr int kPerLane = (kSweepTileCap + kThreads - 1) / kThreads;  // tile entries per lane
 constexpr int kMaxRounds = kSweepMaxRounds;
@@ -47,6 +52,16 @@ __device__ __forceinline__ int tile_slot(int b, int nt)
     const int x = b % kXcds, slot = b / kXcds;
     const int full = nt / kXcds, rem = nt % kXcds;
     return x * full + min(x, rem) + slot;
+}
+
+// f(std::integral_constant<int, I>{}) for I = B, B + 1, ..., E - 1
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
 }
 
 struct TileState {
@@ -74,13 +89,17 @@ __device__ __forceinline__ bool entry_ok(uint64_t c, const SweepDesc &sd, const 
     return true;
 }
 
-template <typename V, bool ADJ, int MC>
+template <typename V, bool ADJ, int MC, bool PEN>
 __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
-    V *__restrict__ X, const double2 *__restrict__ Tbuf, SweepDesc sd,
+    V *__restrict__ X, const double2 *__restrict__ Tbuf, const double2 *__restrict__ Ttbuf,
+    const SweepDesc *__restrict__ sdp,
     const int *__restrict__ tiles, const int64_t *__restrict__ goff,
     const uint64_t *__restrict__ code, const int *__restrict__ llist,
     const int *__restrict__ lloff, const int *__restrict__ lanetab)
 {
+    // the descriptor is read from device memory: a by-value kernel argument
+    // that lambdas capture would be copied to scratch
+    const SweepDesc &sd = *sdp;
     const int M = MC > 0 ? MC : sd.M;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double2 *tile = reinterpret_cast<double2 *>(smem_raw);
@@ -108,7 +127,8 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
     }
     __syncthreads();
 
-    // 1. diagonal blocks of T_j and the tile of C
+    // 1. diagonal blocks of T_j (and a zero entry after them) and the tile of C
+    if (threadIdx.x == 0) tdiag[sd.tdiag] = make_double2(0.0, 0.0);
     for (int j = 0; j < M; ++j) {
         const int b = sd.b[j], e = ts.e[j], o = ts.o[j], d = sd.d[j];
         const double2 *Tj = Tbuf + sd.moff[j];
@@ -118,9 +138,11 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
                 (r < e && c < e) ? Tj[(o + r) + (int64_t)d * (o + c)] : make_double2(0.0, 0.0);
         }
     }
+    // this lane's pencil (pencil form of the local solve)
+    const int pen_item = PEN ? lanetab[threadIdx.x] : -1;
     // this lane's local-solve work, all levels at once (one memory latency)
     int pk[kMaxRounds];
-    if (sd.packed) {
+    if (!PEN && sd.packed) {
 #pragma unroll
         for (int rr = 0; rr < kMaxRounds; ++rr)
             pk[rr] = rr < sd.rounds
@@ -236,7 +258,131 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
         }
         tile[t] = cdiv(num, den);
     };
-    if (sd.packed) {
+    if (PEN) {
+        // Pencil form: lane = one pencil along mode 0 (the tile's entries that
+        // differ only in loc_0), kept in registers as it is solved; a wave holds
+        // pencils of one index sum g over the other modes, so at local level L
+        // all its lanes solve entry loc_0 = L - g: the mode-0 terms use
+        // wave-uniform coefficients T_0[loc_0, k] and the lane's own registers,
+        // only the other modes read neighbours from LDS.
+        const int lead = __builtin_amdgcn_readfirstlane(pen_item);
+        const bool has = pen_item >= 0;
+        const int t0 = has ? (pen_item & kPackMask) : 0;
+        const uint64_t c = has ? (uint64_t)(pen_item >> kPackShift) : 0;
+        const uint64_t cl = lead >= 0 ? (uint64_t)(lead >> kPackShift) : 0;
+        constexpr int kD = 2 * (MC > 1 ? MC - 1 : 1);  // first two neighbours per other mode
+        int dep[kD];  // per neighbour: coefficient slot << 16 | entry offset (zero slot if none)
+        int g = 0;
+        bool act = has;
+        double2 sigma = ts.shift;  // the diagonal terms of the other modes
+#pragma unroll
+        for (int j = 1; j < M; ++j) {
+            const int w = sd.bitw[j];
+            const uint64_t m = (1ull << w) - 1ull;
+            g += w ? (int)((cl >> sd.bitoff[j]) & m) : 0;
+            const int loc = w ? (int)((c >> sd.bitoff[j]) & m) : 0;
+            act = act && loc < ts.e[j];
+        }
+#pragma unroll
+        for (int j = 1; j < M; ++j) {
+            const int w = sd.bitw[j];
+            const int loc = w ? (int)((c >> sd.bitoff[j]) & ((1ull << w) - 1ull)) : 0;
+            const int b = sd.b[j], td = sd.tdoff[j];
+            const double2 lam = tdiag[td + loc + b * loc];
+            sigma = cadd(sigma, ADJ ? cconj(lam) : lam);
+            const int nq = ADJ ? loc : ts.e[j] - 1 - loc;
+#pragma unroll
+            for (int q = 1; q <= 2; ++q) {
+                const bool ok = act && nq >= q;
+                const int slot = ok ? td + (ADJ ? (loc - q) + b * loc : loc + b * (loc + q)) : sd.tdiag;
+                dep[2 * (j - 1) + q - 1] = (slot << 16) | (ok ? q * sd.ls[j] : 0);
+            }
+        }
+        g = __builtin_amdgcn_readfirstlane(g);
+        const int e0 = __builtin_amdgcn_readfirstlane(ts.e[0]);
+        const int64_t r0 = __builtin_amdgcn_readfirstlane(ts.o[0]);
+        const int64_t d0 = sd.d[0];
+        // column K of T_0 (adjoint) or row K of T_0 (= column K of T_0^T): the
+        // mode-0 coefficients of entry K are contiguous there
+        const double2 *Tcol = (ADJ ? Tbuf : Ttbuf) + sd.moff[0] + r0;
+        double2 y[kPen];
+#pragma unroll
+        for (int i = 0; i < kPen; ++i) y[i] = make_double2(0.0, 0.0);
+        // the entry at mode-0 position K, with K a compile-time constant: the
+        // pencil registers are then addressed statically
+        auto entry = [&](auto kc) __attribute__((always_inline)) {
+            constexpr int K = decltype(kc)::value;
+            const int t = t0 + K;
+            const double2 *cf = Tcol + d0 * (r0 + K);
+            double2 num = tile[t];
+            if (ADJ) {
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk) num = csub(num, cmul(cconj(cf[kk]), y[kk]));
+            } else {
+                // past the block end y is zero; the coefficient index stays in it
+#pragma unroll
+                for (int kb = (K + 1) & ~(kChunk0 - 1); kb < kPen; kb += kChunk0) {
+                    if (kb >= e0) break;  // uniform
+#pragma unroll
+                    for (int kk = kb; kk < kb + kChunk0; ++kk)
+                        if (kk > K) num = csub(num, cmul(cf[min(kk, e0 - 1)], y[kk]));
+                }
+            }
+            double2 yk = make_double2(0.0, 0.0);
+            if (act) {
+                const double2 lam0 = cf[K];
+                const double2 den = cadd(sigma, ADJ ? cconj(lam0) : lam0);
+#pragma unroll
+                for (int i = 0; i < kD; ++i) {
+                    if (i >= 2 * (M - 1)) break;
+                    const double2 a = tdiag[dep[i] >> 16];
+                    const double2 yn = tile[ADJ ? t - (dep[i] & 0xffff) : t + (dep[i] & 0xffff)];
+                    num = csub(num, ADJ ? cmul(cconj(a), yn) : cmul(a, yn));
+                }
+                if (sd.pen_long) {  // neighbours beyond the second (blocks longer than 3)
+#pragma unroll 1
+                    for (int j = 1; j < M; ++j) {
+                        const int w = sd.bitw[j];
+                        const int loc = w ? (int)((c >> sd.bitoff[j]) & ((1ull << w) - 1ull)) : 0;
+                        const int b = sd.b[j], lsj = sd.ls[j];
+                        const double2 *Td = tdiag + sd.tdoff[j];
+                        const int nq = ADJ ? loc : ts.e[j] - 1 - loc;
+                        for (int q = 3; q <= nq; ++q)
+                            num = ADJ ? csub(num, cmul(cconj(Td[(loc - q) + b * loc]), tile[t - q * lsj]))
+                                      : csub(num, cmul(Td[loc + b * (loc + q)], tile[t + q * lsj]));
+                    }
+                }
+                yk = cdiv_scaled(num, den);
+                tile[t] = yk;
+            }
+            y[K] = yk;
+        };
+        // A wave is active at the e0 local levels g .. g + e0 - 1, one entry
+        // each; before and after them it only takes part in the barriers, so
+        // every wave passes the same nll barriers.
+        const int before = lead < 0 ? sd.nll : (ADJ ? g : sd.nll - g - e0);
+        for (int i = 0; i < before; ++i) __syncthreads();
+        if (lead >= 0) {
+            if (ADJ) {
+                static_for<0, kPen>([&](auto kc) __attribute__((always_inline)) {
+                    if (decltype(kc)::value < e0) {
+                        entry(kc);
+                        __syncthreads();
+                    }
+                });
+            } else {
+                static_for<0, kPen>([&](auto kc) __attribute__((always_inline)) {
+                    constexpr int K = kPen - 1 - decltype(kc)::value;
+                    if (K < e0) {
+                        entry(std::integral_constant<int, K>{});
+                        __syncthreads();
+                    }
+                });
+            }
+            const int after = ADJ ? sd.nll - g - e0 : g;
+            for (int i = 0; i < after; ++i) __syncthreads();
+        }
+    } else if (sd.packed) {
         // rounds in processing order; a barrier wherever the local level changes
 #pragma unroll
         for (int rr = 0; rr < kMaxRounds; ++rr) {
@@ -277,21 +423,21 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
     }
 }
 
-template <typename V, bool ADJ>
-hipError_t run_sweep(const sylt_plan_s &p, V *X, hipStream_t s)
+template <typename V, bool ADJ, bool PEN>
+hipError_t run_sweep_as(const sylt_plan_s &p, V *X, hipStream_t s)
 {
     const SweepPlan &sp = p.sweep;
-    decltype(&sweep_tile_kernel<V, ADJ, 0>) ker;
+    decltype(&sweep_tile_kernel<V, ADJ, 0, PEN>) ker;
     switch (sp.desc.M) {
-        case 1: ker = sweep_tile_kernel<V, ADJ, 1>; break;
-        case 2: ker = sweep_tile_kernel<V, ADJ, 2>; break;
-        case 3: ker = sweep_tile_kernel<V, ADJ, 3>; break;
-        case 4: ker = sweep_tile_kernel<V, ADJ, 4>; break;
-        case 5: ker = sweep_tile_kernel<V, ADJ, 5>; break;
-        case 6: ker = sweep_tile_kernel<V, ADJ, 6>; break;
-        case 7: ker = sweep_tile_kernel<V, ADJ, 7>; break;
-        case 8: ker = sweep_tile_kernel<V, ADJ, 8>; break;
-        default: ker = sweep_tile_kernel<V, ADJ, 0>; break;
+        case 1: ker = sweep_tile_kernel<V, ADJ, 1, PEN>; break;
+        case 2: ker = sweep_tile_kernel<V, ADJ, 2, PEN>; break;
+        case 3: ker = sweep_tile_kernel<V, ADJ, 3, PEN>; break;
+        case 4: ker = sweep_tile_kernel<V, ADJ, 4, PEN>; break;
+        case 5: ker = sweep_tile_kernel<V, ADJ, 5, PEN>; break;
+        case 6: ker = sweep_tile_kernel<V, ADJ, 6, PEN>; break;
+        case 7: ker = sweep_tile_kernel<V, ADJ, 7, PEN>; break;
+        case 8: ker = sweep_tile_kernel<V, ADJ, 8, PEN>; break;
+        default: ker = sweep_tile_kernel<V, ADJ, 0, PEN>; break;
     }
     if (sp.lds_bytes > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)ker,
@@ -305,10 +451,17 @@ hipError_t run_sweep(const sylt_plan_s &p, V *X, hipStream_t s)
         const int64_t b0 = sp.level_off[lv], b1 = sp.level_off[lv + 1];
         if (b1 <= b0) continue;
         hipLaunchKernelGGL(ker, dim3((unsigned)(b1 - b0)), dim3(kThreads), sp.lds_bytes, s, X,
-                           p.dT, sp.desc, sp.d_tiles + b0, sp.d_goff, sp.d_code, sp.d_llist,
+                           p.dT, p.dTt, sp.d_desc, sp.d_tiles + b0, sp.d_goff, sp.d_code, sp.d_llist,
                            sp.d_lloff, sp.d_lanetab);
     }
     return hipGetLastError();
+}
+
+template <typename V, bool ADJ>
+hipError_t run_sweep(const sylt_plan_s &p, V *X, hipStream_t s)
+{
+    if (p.sweep.desc.penc && p.sweep.desc.M > kSweepPencilModes) return hipErrorInvalidValue;
+    return p.sweep.desc.penc ? run_sweep_as<V, ADJ, true>(p, X, s) : run_sweep_as<V, ADJ, false>(p, X, s);
 }
 
 }  // namespace

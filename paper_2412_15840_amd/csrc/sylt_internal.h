@@ -18,6 +18,8 @@ constexpr int kMaxGroup = 24;     // modes fused in one transform pass (n >= 2 e
 constexpr int kSweepTileCap = 9728;   // sweep tile entries (with diagonal blocks <= 160 KB LDS)
 constexpr int kSweepThreads = 1024;   // lanes of a sweep workgroup
 constexpr int kSweepMaxRounds = 32;   // local-solve rounds held per lane in registers
+constexpr int kSweepPencilMax = 20;   // longest mode-0 pencil held in one lane's registers
+constexpr int kSweepPencilModes = 8;  // most tiled modes of the pencil form
 
 // ----------------------------------------------------------------- complex
 // double2 / float2 hold (re, im).  All products are written as explicit fused
@@ -73,6 +75,18 @@ __host__ __device__ inline double2 cdiv(double2 a, double2 b)
     return make_double2((a.x * r + a.y) / den, (a.y * r - a.x) / den);
 }
 
+// a / b with one division: b is scaled by an exact power of two 2^-e that
+// brings its larger component into [1/2, 1), then a / b = (a conj(b') / |b'|^2) 2^-e.
+__device__ inline double2 cdiv_scaled(double2 a, double2 b)
+{
+    int e;
+    frexp(fmax(fabs(b.x), fabs(b.y)), &e);
+    const double bx = ldexp(b.x, -e), by = ldexp(b.y, -e);
+    const double inv = 1.0 / fma(bx, bx, by * by);
+    const double px = fma(a.x, bx, a.y * by), py = fma(a.y, bx, -(a.x * by));
+    return make_double2(ldexp(px * inv, -e), ldexp(py * inv, -e));
+}
+
 // principal square root: for z = x + iy with t = sqrt((|z| + |x|)/2),
 // sqrt(z) = (t, y/(2t)) when x >= 0 and (|y|/(2t), sign(y) t) otherwise.
 __host__ __device__ inline double2 csqrt_(double2 z)
@@ -125,6 +139,10 @@ struct SweepDesc {
     int nll;                     // local levels
     int tdiag;                   // total entries of the diagonal blocks
     int packed;                  // local-solve work in the per-lane packed table
+    int penc;                    // local solve by mode-0 pencils, one per lane (the
+                                 // table then holds one pencil per lane)
+    int pen_long;                // some other mode has a block longer than 3
+    int zero_slot;               // LDS entry (after the diagonal blocks) that holds 0
     int rounds;                  // rounds of that table (levels wider than the
                                  // workgroup take several rounds)
     int round_level[kSweepMaxRounds];  // local level of each round, ascending
@@ -134,6 +152,7 @@ struct SweepDesc {
 
 struct SweepPlan {
     SweepDesc desc{};
+    SweepDesc *d_desc = nullptr;     // device copy of desc
     std::vector<int64_t> level_off;  // tile-level offsets into tiles (size nlev + 1)
     int *d_tiles = nullptr;          // tile ids sorted by tile level
     int64_t *d_goff = nullptr;       // global offset of each local entry
@@ -166,6 +185,7 @@ struct sylt_plan_s {
     double2 *dU = nullptr;           // U_k
     double2 *dUh = nullptr;          // U_k^* (conjugate transpose), column-major
     double2 *dT = nullptr;           // T_k
+    double2 *dTt = nullptr;          // T_k^T (rows of T_k contiguous)
     float2 *dU32 = nullptr;          // complex64 copies
     float2 *dUh32 = nullptr;
     int *dStatus = nullptr;          // per-mode Schur status

@@ -16,6 +16,9 @@ What it computes (Cuesta & de la Hoz, arXiv 2412.15840):
   * ``apply``            -- the Kronecker-sum operator sum_j A_j []_j X.
   * ``apply_at``         -- that operator at a few chosen entries (pure Python).
   * ``separation``       -- min over multi-indices of |sum_j lambda_{j,i_j}|.
+  * ``evolve``           -- Theorem 1 in Schur form (eqs. e:sylvesterNDG and
+                            e:G): X(t) of X_t = sum_j A_j []_j X + B from X(0),
+                            with exp(t T_j) from SciPy's expm (eq. e:exptAj).
 
 All tensors are flat complex128 numpy arrays in column-major order (mode 1
 fastest), the paper's linear index (eq. e:index).  Matrices are (n, n) arrays.
@@ -195,6 +198,27 @@ def solve_adjoint_factored(n, U_list, T_list, W):
     PU, PT = _PtrArray(U_list), _PtrArray(T_list)
     lib().ora_solve_adjoint_factored(len(n), dp, PU.ptr, PT.ptr, G.ctypes.data)
     return G
+
+
+def evolve_factored(n, U_list, T_list, B, X0, t):
+    """Theorem 1 with the Schur factors, in the order of eqs. e:sylvesterNDG
+    and e:G: C = U^*-chain(B), Y(0) = U^*-chain(X(0)),
+    G = exp(tT_N) []_N ( ... exp(tT_1) []_1 (sum_j T_j []_j Y(0) + C)) - C,
+    then the sweep for sum_j T_j []_j Y = G and X(t) = U-chain(Y)."""
+    C = transform(n, U_list, B, adjoint=True)
+    Y0 = transform(n, U_list, X0, adjoint=True)
+    G = apply(n, T_list, Y0) + C
+    for k, T in enumerate(T_list):
+        G = mode_product(n, k, scipy.linalg.expm(t * np.asarray(T, np.complex128)), G)
+    G = G - C
+    Y, _ = sweep(n, T_list, G)
+    return transform(n, U_list, Y, adjoint=False)
+
+
+def evolve(n, A_list, B, X0, t):
+    """X(t) for X_t = sum_j A_j []_j X + B, X(0) = X0 (Theorem 1)."""
+    U, T = factors(A_list)
+    return evolve_factored(n, U, T, B, X0, t)
 
 
 def solve_adjoint(n, A_list, W):

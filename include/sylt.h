@@ -182,6 +182,29 @@ int sylt_solve_backward(sylt_plan p, const double *X, const double *GX, double *
                         double *const *GA, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * sylt_evolve -- time evolution by Theorem 1 in Schur form (eqs.
+ * e:sylvesterNDG and e:G, from the proof's exp(tA) of a Kronecker sum): the
+ * value at time t of the solution of X_t = sum_k A_k x_k X + B, X(0) = X0.
+ * With C = U^*-chain(B) and Y(0) = U^*-chain(X0) it forms
+ *   G = exp(t T_N) x_N ( ... exp(t T_1) x_1 (sum_k T_k x_k Y(0) + C)) - C,
+ * solves sum_k T_k x_k Y = G by the sweep and returns X = U-chain(Y).  The
+ * exp(t T_k) (eq. e:exptAj) are formed on the device by scaling and squaring
+ * of a Taylor series on the triangular T_k; singleton modes contribute the
+ * scalar exp(t a_k).  Uses only the plan's U_k and T_k (works for plans from
+ * sylt_plan_from_factors without A).
+ * B, X0: complex128 device tensors, not modified.  X: complex128 output; may
+ * alias X0 or B.  t: any finite real.  ws: caller device workspace of at least
+ * sylt_evolve_workspace_bytes(p) bytes (two complex128 tensors), not
+ * overlapping B, X0 or X.  Enqueued on `stream`, no synchronisation.
+ * INVALID_ARG for a NULL pointer or non-finite t; WORKSPACE if ws is too small.
+ */
+int sylt_evolve(sylt_plan p, double t, const double *B, const double *X0, double *X, void *ws,
+                size_t ws_bytes, void *stream);
+
+/* Bytes of workspace sylt_evolve needs (negative sylt_status on error). */
+int64_t sylt_evolve_workspace_bytes(sylt_plan p);
+
+/*
  * sylt_plan_describe -- writes a NUL-terminated JSON description of the plan
  * (extents, Schur separation, the fused transform passes with their tile
  * shapes and launch counts, the sweep's block sizes, tile levels and local

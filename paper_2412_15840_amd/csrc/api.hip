@@ -395,6 +395,10 @@ void free_plan(sylt_plan_s *p)
     hipFree(p->dUh);
     hipFree(p->dT);
     hipFree(p->dTt);
+    hipFree(p->dTneg);
+    hipFree(p->dE);
+    hipFree(p->dEw);
+    hipFree(p->dEvo);
     hipFree(p->dU32);
     hipFree(p->dUh32);
     hipFree(p->dStatus);
@@ -437,6 +441,10 @@ int init_plan(sylt_plan_s *p, int N, const int64_t *n)
     SYLT_TRY(hipMalloc(&p->dUh, mb));
     SYLT_TRY(hipMalloc(&p->dT, mb));
     SYLT_TRY(hipMalloc(&p->dTt, p->mtotal * sizeof(double2)));
+    SYLT_TRY(hipMalloc(&p->dTneg, p->mtotal * sizeof(double2)));
+    SYLT_TRY(hipMalloc(&p->dE, p->mtotal * sizeof(double2)));
+    SYLT_TRY(hipMalloc(&p->dEw, 3 * p->mtotal * sizeof(double2)));
+    SYLT_TRY(hipMalloc(&p->dEvo, 4 * sizeof(double2)));
     SYLT_TRY(hipMalloc(&p->dU32, p->mtotal * sizeof(float2)));
     SYLT_TRY(hipMalloc(&p->dUh32, p->mtotal * sizeof(float2)));
     SYLT_TRY(hipMalloc(&p->dStatus, std::max(1, N) * sizeof(int)));
@@ -730,6 +738,43 @@ int sylt_solve(sylt_plan p, const sylt_opts *o, const double *B, double *X, void
         info->rel_residual = rel;
     }
     return st;
+}
+
+int64_t sylt_evolve_workspace_bytes(sylt_plan p)
+{
+    if (!p) return SYLT_E_INVALID_ARG;
+    return 2 * p->ntot * (int64_t)sizeof(double2);
+}
+
+int sylt_evolve(sylt_plan p, double t, const double *B, const double *X0, double *X, void *ws,
+                size_t ws_bytes, void *stream)
+{
+    if (!p || !B || !X0 || !X || !std::isfinite(t)) return SYLT_E_INVALID_ARG;
+    if (!ws || (int64_t)ws_bytes < sylt_evolve_workspace_bytes(p)) return SYLT_E_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = p->ntot;
+    double2 *Xc = reinterpret_cast<double2 *>(X);
+    double2 *C = static_cast<double2 *>(ws);
+    double2 *W = C + n;
+    SYLT_TRY(launch_expm(*p, t, s));
+    // C = U^*-chain(B) first, so that X may alias B
+    SYLT_TRY(launch_copy_c128(C, reinterpret_cast<const double2 *>(B), n, s));
+    SYLT_TRY(launch_transform(*p, SYLT_TO_SCHUR, SYLT_FP64, C, s));
+    // Y(0) = U^*-chain(X0), held in X
+    if (X != X0) SYLT_TRY(launch_copy_c128(Xc, reinterpret_cast<const double2 *>(X0), n, s));
+    SYLT_TRY(launch_transform(*p, SYLT_TO_SCHUR, SYLT_FP64, Xc, s));
+    // W = sum_k T_k x_k Y(0) + C, as C - sum_k (-T_k) x_k Y(0)
+    if (!p->rpasses.empty())
+        SYLT_TRY(launch_residual_with(*p, p->dTneg, C, Xc, W, nullptr, nullptr, s));
+    else  // every mode is a singleton: W = C + (sum a_k) Y(0)
+        SYLT_TRY(launch_lincomb(W, C, Xc, p->dEvo + 2, n, s));
+    // G = exp(t T_N) x_N ( ... exp(t T_1) x_1 W) - C, in X
+    SYLT_TRY(launch_transform_with(*p, p->dE, W, s));
+    SYLT_TRY(launch_lincomb(Xc, W, C, p->dEvo, n, s));
+    // sum_k T_k x_k Y = G, then X(t) = U-chain(Y)
+    SYLT_TRY(launch_sweep(*p, SYLT_OP_N, SYLT_FP64, Xc, s));
+    SYLT_TRY(launch_transform(*p, SYLT_FROM_SCHUR, SYLT_FP64, Xc, s));
+    return SYLT_OK;
 }
 
 int sylt_solve_backward(sylt_plan p, const double *X, const double *GX, double *GB,

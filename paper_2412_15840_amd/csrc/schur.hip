@@ -221,7 +221,7 @@ struct PrepJobs {
 __global__ void prepare_factors_kernel(PrepJobs jobs, const double2 *__restrict__ U,
                                        double2 *__restrict__ Uh, float2 *__restrict__ U32,
                                        float2 *__restrict__ Uh32, const double2 *__restrict__ T,
-                                       double2 *__restrict__ Tt)
+                                       double2 *__restrict__ Tt, double2 *__restrict__ Tneg)
 {
     const int job = blockIdx.x;
     const int n = jobs.n[job];
@@ -234,6 +234,8 @@ __global__ void prepare_factors_kernel(PrepJobs jobs, const double2 *__restrict_
         U32[off + idx] = make_float2((float)u.x, (float)u.y);
         Uh32[off + idx] = make_float2((float)ut.x, (float)-ut.y);
         Tt[off + idx] = T[off + j + (int64_t)n * i];
+        const double2 tv = T[off + idx];
+        Tneg[off + idx] = make_double2(-tv.x, -tv.y);
     }
 }
 
@@ -268,7 +270,7 @@ hipError_t launch_prepare_factors(const sylt_plan_s &p, hipStream_t s)
         ++jobs.count;
     }
     hipLaunchKernelGGL(prepare_factors_kernel, dim3(jobs.count), dim3(256), 0, s, jobs, p.dU,
-                       p.dUh, p.dU32, p.dUh32, p.dT, p.dTt);
+                       p.dUh, p.dU32, p.dUh32, p.dT, p.dTt, p.dTneg);
     return hipGetLastError();
 }
 

@@ -186,6 +186,10 @@ struct sylt_plan_s {
     double2 *dUh = nullptr;          // U_k^* (conjugate transpose), column-major
     double2 *dT = nullptr;           // T_k
     double2 *dTt = nullptr;          // T_k^T (rows of T_k contiguous)
+    double2 *dTneg = nullptr;        // -T_k
+    double2 *dE = nullptr;           // exp(t T_k) of the last evolution
+    double2 *dEw = nullptr;          // three work matrices per mode for exp(t T_k)
+    double2 *dEvo = nullptr;         // four device scalars of the last evolution
     float2 *dU32 = nullptr;          // complex64 copies
     float2 *dUh32 = nullptr;
     int *dStatus = nullptr;          // per-mode Schur status
@@ -210,6 +214,18 @@ hipError_t launch_sweep(const sylt_plan_s &p, int op, int precision, void *X, hi
 // reduced into norms2_dev[0..1] (device).
 hipError_t launch_residual(const sylt_plan_s &p, const double2 *B, const double2 *X, double2 *R64,
                            float2 *R32, double *norms2_dev, hipStream_t s);
+// the same with the matrices M_k of Mbuf (offsets p.moff) in place of A_k
+hipError_t launch_residual_with(const sylt_plan_s &p, const double2 *Mbuf, const double2 *B,
+                                const double2 *X, double2 *R64, float2 *R32, double *norms2_dev,
+                                hipStream_t s);
+// chain of mode products with the matrices of M (offsets p.moff; singleton modes skipped)
+hipError_t launch_transform_with(const sylt_plan_s &p, const double2 *M, double2 *X, hipStream_t s);
+// E_k = exp(t T_k) for every mode into p.dE, and p.dEvo = {prod of the
+// singleton modes' exp(t a_k), -1, 1, sum of the singleton modes' a_k}
+hipError_t launch_expm(const sylt_plan_s &p, double t, hipStream_t s);
+// out = c[0] x + c[1] y with device scalars c (out may alias x or y)
+hipError_t launch_lincomb(double2 *out, const double2 *x, const double2 *y, const double2 *c,
+                          int64_t n, hipStream_t s);
 hipError_t launch_axpy_c64(double2 *X, const float2 *D, int64_t n, int assign, hipStream_t s);
 hipError_t launch_convert_c128_c64(float2 *out, const double2 *in, int64_t n, hipStream_t s);
 hipError_t launch_copy_c128(double2 *out, const double2 *in, int64_t n, hipStream_t s);

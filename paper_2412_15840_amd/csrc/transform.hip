@@ -778,8 +778,24 @@ hipError_t launch_transform(const sylt_plan_s &p, int dir, int precision, void *
     return hipSuccess;
 }
 
+hipError_t launch_transform_with(const sylt_plan_s &p, const double2 *M, double2 *X, hipStream_t s)
+{
+    for (const PassDesc &pa : p.passes) {
+        const hipError_t e = run_transform_pass<double2>(pa, X, M, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_residual(const sylt_plan_s &p, const double2 *B, const double2 *X, double2 *R64,
                            float2 *R32, double *norms2_dev, hipStream_t s)
+{
+    return launch_residual_with(p, p.dA, B, X, R64, R32, norms2_dev, s);
+}
+
+hipError_t launch_residual_with(const sylt_plan_s &p, const double2 *Mbuf, const double2 *B,
+                                const double2 *X, double2 *R64, float2 *R32, double *norms2_dev,
+                                hipStream_t s)
 {
     const int P = (int)p.rpasses.size();
     // plan scratch: [part_b (max tiles)] [part_r (max tiles)]
@@ -802,7 +818,7 @@ hipError_t launch_residual(const sylt_plan_s &p, const double2 *B, const double2
         e = allow_lds(KER, lds);                                                                \
         if (e != hipSuccess) return e;                                                          \
         hipLaunchKernelGGL(KER, dim3((unsigned)tiles), dim3(kThreads), lds, s, B, X, R64,       \
-                           last ? R32 : nullptr, p.dA, pa, sing, first, last, part_b, part_r);  \
+                           last ? R32 : nullptr, Mbuf, pa, sing, first, last, part_b, part_r);  \
     } while (0)
         switch (pa.uniform_n) {
             case 2: SYLT_RLAUNCH(residual_pass_kernel<2>); break;

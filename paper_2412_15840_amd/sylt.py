@@ -12,6 +12,7 @@ paper's linear index, Section 2.2 eq. e:index):
     residual(plan, B, X)              sylt_residual
     solve(plan, B)                    sylt_solve
     solve_backward(plan, X, GX)       sylt_solve_backward
+    evolve(plan, t, B, X0)            sylt_evolve
 
 Matrices passed to / returned from these functions are ordinary (n, n) torch
 tensors with their mathematical meaning M[i, m]; the binding converts them to
@@ -78,6 +79,9 @@ def lib():
         L.sylt_solve.argtypes = [_vp, ctypes.POINTER(_Opts), _vp, _vp, _vp, ctypes.c_size_t, _vp,
                                  ctypes.POINTER(_Info)]
         L.sylt_solve_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.sylt_evolve.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.sylt_evolve_workspace_bytes.argtypes = [_vp]
+        L.sylt_evolve_workspace_bytes.restype = ctypes.c_int64
         L.sylt_plan_describe.argtypes = [_vp, ctypes.c_char_p, ctypes.c_size_t]
         L.sylt_status_string.argtypes = [ctypes.c_int]
         L.sylt_status_string.restype = ctypes.c_char_p
@@ -261,6 +265,21 @@ def solve_backward(plan, X, GX, want_A=True, out=None, stream=None):
 
 
 # ----------------------------------------------------------- torch facing
+def evolve(plan, t, B, X0, out=None, workspace=None, stream=None):
+    """X(t) for X_t = sum_k A_k x_k X + B, X(0) = X0 (Theorem 1), flat
+    complex128 tensors; out may be B or X0."""
+    _flat(B, torch.complex128)
+    _flat(X0, torch.complex128)
+    X = out if out is not None else torch.empty_like(B)
+    nbytes = lib().sylt_evolve_workspace_bytes(plan.handle)
+    _check(nbytes if nbytes < 0 else 0, "sylt_evolve_workspace_bytes")
+    ws = workspace if workspace is not None else torch.empty(nbytes, dtype=torch.uint8,
+                                                             device=B.device)
+    _check(lib().sylt_evolve(plan.handle, float(t), B.data_ptr(), X0.data_ptr(), X.data_ptr(),
+                             ws.data_ptr(), ws.numel(), _stream(stream)), "sylt_evolve")
+    return X
+
+
 class SchurSolve(torch.autograd.Function):
     """X = A^{-1} B for row-major torch tensors.
 

@@ -80,6 +80,9 @@ def test_null_pointers_rejected(L):
     assert L.sylt_workspace_bytes(None, 0) == -1
     assert L.sylt_plan_separation(None, None) == -1
     assert L.sylt_plan_get_factors(None, 0, None, None, None) == -1
+    assert L.sylt_evolve(None, ctypes.c_double(0.1), None, None, None, None, 0, None) == -1
+    L.sylt_evolve_workspace_bytes.restype = ctypes.c_int64
+    assert L.sylt_evolve_workspace_bytes(None) == -1
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

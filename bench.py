@@ -8,7 +8,8 @@ workload is N = 7, n_k = 19 (893,871,739 complex128 entries, 14.3 GB per
 tensor); inputs are seeded synthetic tensors already resident in HBM when the
 timed region starts.  The mixed-precision solve (FP32 transforms, FP64 sweep,
 FP64 residual, iterative refinement to a 1e-12 relative residual) is timed on
-the same inputs and reported beside it.
+the same inputs and reported beside it, and so is the time evolution of
+Theorem 1 (sylt_evolve at t = 0.1).
 
 Prints ONE JSON line (rank 0).  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C3b]
@@ -39,6 +40,7 @@ def parse():
     ap.add_argument("--workload", default="C3b")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-evolve", action="store_true")
     ap.add_argument("--phase-reps", type=int, default=3)
     return ap.parse_args()
 
@@ -274,6 +276,26 @@ def main():
         log(f"mixed {mixed}")
         del ws, Xm
 
+    # ---------------------------------------------------------- evolution
+    # Theorem 1 at t = 0.1 (sylt_evolve) on the same plan, with X(0) = B (any
+    # seeded input times the same); algorithmic work: four transform chains
+    # (B, X(0), exp(tT), back), the Kronecker-sum apply, the sweep
+    evolve = None
+    if not args.no_evolve:
+        Xe = torch.empty_like(Bd)
+        ws_e = torch.empty(2 * ntot * 16, dtype=torch.uint8, device="cuda")
+        sylt.evolve(plan, 0.1, Bd, Bd, out=Xe, workspace=ws_e)
+        torch.cuda.synchronize()
+        t_e = time_events(lambda: sylt.evolve(plan, 0.1, Bd, Bd, out=Xe, workspace=ws_e),
+                          max(1, min(args.steps, 2)), torch)
+        ev_flops = 4 * tr_flops + 8.0 * ntot * sum_n + sw_flops
+        t_e_fp = ev_flops / (FP64_VECTOR_PEAK_TF * 1e12)
+        evolve = {"t": 0.1, "ms": round(t_e, 3), "entries_per_s": ntot / (t_e * 1e-3),
+                  "t_fp64_ms": round(t_e_fp * 1e3, 3),
+                  "binding_roof_frac": round(t_e_fp / (t_e * 1e-3), 4)}
+        log(f"evolve {evolve}")
+        del Xe, ws_e
+
     # ---------------------------------------------------------- CPU oracle
     cpu = None
     if not args.no_cpu:
@@ -293,7 +315,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "solve_roofline": solve_roof,
-        "phases": phases, "kernels": kernels, "mixed": mixed,
+        "phases": phases, "kernels": kernels, "mixed": mixed, "evolve": evolve,
         "plan": {"transform_passes": [p["extents"] for p in desc["transform_passes"]],
                  "sweep_block": desc["sweep"]["block"], "sweep_tile_levels": n_lvl,
                  "sep": desc["sep"]},

@@ -1,6 +1,7 @@
 // C ABI of libsylt: argument validation, plan construction (Schur factors,
 // separation, transform-pass and sweep-tile planning), and the solve drivers.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -395,6 +396,8 @@ void free_plan(sylt_plan_s *p)
     hipFree(p->dUh);
     hipFree(p->dT);
     hipFree(p->dTt);
+    hipFree(p->dslo);
+    hipFree(p->dshi);
     hipFree(p->dTneg);
     hipFree(p->dE);
     hipFree(p->dEw);
@@ -458,6 +461,42 @@ int init_plan(sylt_plan_s *p, int N, const int64_t *n)
 }
 
 // separation into the tail of the scratch, then one synchronisation
+// Remark 1: if every T_k is diagonal to rounding (each strictly upper entry
+// at most 64 n_k eps max|T_k|, as for normal A_k), the sweep becomes the
+// Hadamard product with the inverse eigenvalue sums; build its two tables.
+int plan_diagonal(sylt_plan_s *p, hipStream_t s)
+{
+    p->diagT = false;
+    if (p->M == 0) return SYLT_OK;
+    std::vector<double2> T(p->mtotal);
+    SYLT_TRY(hipMemcpyAsync(T.data(), p->dT, p->mtotal * sizeof(double2), hipMemcpyDeviceToHost, s));
+    SYLT_TRY(hipStreamSynchronize(s));
+    for (int j = 0; j < p->M; ++j) {
+        const int n = p->cdim[j];
+        const double2 *Tj = T.data() + p->moff[p->cmode[j]];
+        double big = 0.0, off = 0.0;
+        for (int c = 0; c < n; ++c)
+            for (int r = 0; r <= c; ++r) {
+                const double a = std::hypot(Tj[r + (int64_t)n * c].x, Tj[r + (int64_t)n * c].y);
+                big = std::max(big, a);
+                if (r < c) off = std::max(off, a);
+            }
+        if (off > 64.0 * n * DBL_EPSILON * big) return SYLT_OK;
+    }
+    // low table: the longest prefix of compressed modes with at most 2^16 entries
+    int split = 0;
+    int64_t lo = 1;
+    while (split < p->M && lo * p->cdim[split] <= (1 << 16)) lo *= p->cdim[split++];
+    p->dsplit = split;
+    p->dlo = lo;
+    p->dhi = p->ntot / lo;
+    SYLT_TRY(hipMalloc(&p->dslo, p->dlo * sizeof(double2)));
+    SYLT_TRY(hipMalloc(&p->dshi, p->dhi * sizeof(double2)));
+    SYLT_TRY(launch_diag_tables(*p, s));
+    p->diagT = true;
+    return SYLT_OK;
+}
+
 int finish_plan(sylt_plan_s *p, hipStream_t s, bool check_schur)
 {
     SYLT_TRY(launch_prepare_factors(*p, s));
@@ -471,7 +510,7 @@ int finish_plan(sylt_plan_s *p, hipStream_t s, bool check_schur)
         for (int k = 0; k < p->N; ++k)
             if (st[k]) return SYLT_E_NO_CONVERGENCE;
     if (!(p->sep > 0.0)) return SYLT_E_SINGULAR;
-    return SYLT_OK;
+    return plan_diagonal(p, s);
 }
 
 int check_ptrs(int N, const double *const *P)
@@ -618,6 +657,7 @@ int sylt_plan_describe(sylt_plan p, char *buf, size_t len)
          ",\"tiles\":" + std::to_string(p->sweep.level_off.empty() ? 0 : p->sweep.level_off.back()) +
          ",\"tile_levels\":" + std::to_string(launches) + ",\"local_levels\":" + std::to_string(sd.nll) +
          ",\"local_solve\":\"" + (sd.penc ? "pencil" : sd.packed ? "packed" : "levels") + "\"" +
+         ",\"diagonal\":" + (p->diagT ? "true" : "false") +
          ",\"lds_bytes\":" + std::to_string(p->sweep.lds_bytes) + "}}";
     const size_t n = std::min(len - 1, s.size());
     memcpy(buf, s.data(), n);

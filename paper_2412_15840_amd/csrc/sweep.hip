@@ -24,6 +24,7 @@
 // coefficients.
 #include "sylt_internal.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace sylt {
@@ -63,6 +64,13 @@ __device__ __forceinline__ void static_for(F &&f)
         static_for<B + 1, E>(f);
     }
 }
+
+struct DiagModes {
+    int d[kMaxModes];
+    int64_t moff[kMaxModes];
+    int nsing;
+    int64_t singoff[kMaxModes];
+};
 
 struct TileState {
     int o[kMaxModes];
@@ -464,12 +472,90 @@ hipError_t run_sweep(const sylt_plan_s &p, V *X, hipStream_t s)
     return p.sweep.desc.penc ? run_sweep_as<V, ADJ, true>(p, X, s) : run_sweep_as<V, ADJ, false>(p, X, s);
 }
 
+// Remark 1 (eq. e:yi1i2iNdiag): with every T_j diagonal the sweep is
+// y_i = c_i / (lambda_{1,i_1} + ... + lambda_{N,i_N}), one streaming pass.
+template <typename V, bool ADJ>
+__global__ void __launch_bounds__(256) diag_sweep_kernel(V *__restrict__ X,
+                                                         const double2 *__restrict__ slo,
+                                                         const double2 *__restrict__ shi, int64_t lo,
+                                                         int64_t ntot)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntot;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t q, r;
+        if (ntot <= 0xffffffffll) {  // 32-bit quotient when the index fits
+            q = (uint32_t)i / (uint32_t)lo;
+            r = (uint32_t)i - (uint32_t)q * (uint32_t)lo;
+        } else {
+            q = i / lo;
+            r = i - q * lo;
+        }
+        const double2 den = cadd(slo[r], shi[q]);
+        X[i] = from_d2<V>(cdiv_scaled(to_d2<V>(X[i]), ADJ ? cconj(den) : den));
+    }
+}
+
+// table[r] = base + sum over modes [j0, j1) of lambda_{j, i_j(r)}, r < count
+__global__ void diag_table_kernel(double2 *table, int64_t count, const double2 *__restrict__ T,
+                                  DiagModes dm, int j0, int j1, int with_singletons)
+{
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < count;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        double2 acc = make_double2(0.0, 0.0);
+        if (with_singletons)
+            for (int i = 0; i < dm.nsing; ++i) acc = cadd(acc, T[dm.singoff[i]]);
+        int64_t rem = r;
+        for (int j = j0; j < j1; ++j) {
+            const int64_t i = rem % dm.d[j];
+            rem /= dm.d[j];
+            acc = cadd(acc, T[dm.moff[j] + i * (dm.d[j] + 1)]);
+        }
+        table[r] = acc;
+    }
+}
+
+template <typename V, bool ADJ>
+hipError_t run_diag_sweep(const sylt_plan_s &p, V *X, hipStream_t s)
+{
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((p.ntot + 255) / 256, 256 * 32));
+    hipLaunchKernelGGL((diag_sweep_kernel<V, ADJ>), dim3((unsigned)blocks), dim3(256), 0, s, X,
+                       p.dslo, p.dshi, p.dlo, p.ntot);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_diag_tables(const sylt_plan_s &p, hipStream_t s)
+{
+    DiagModes dm{};
+    for (int j = 0; j < p.M; ++j) {
+        dm.d[j] = p.cdim[j];
+        dm.moff[j] = p.moff[p.cmode[j]];
+    }
+    for (int k = 0; k < p.N; ++k)
+        if (p.n[k] == 1) dm.singoff[dm.nsing++] = p.moff[k];
+    const int split = p.dsplit;  // compressed modes [0, split) make up the low table
+    auto grid = [](int64_t n) {
+        return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+    };
+    hipLaunchKernelGGL(diag_table_kernel, dim3(grid(p.dlo)), dim3(256), 0, s, p.dslo, p.dlo, p.dT, dm,
+                       0, split, 1);
+    hipLaunchKernelGGL(diag_table_kernel, dim3(grid(p.dhi)), dim3(256), 0, s, p.dshi, p.dhi, p.dT, dm,
+                       split, p.M, 0);
+    return hipGetLastError();
+}
 
 int sweep_max_partial_block() { return kBmax; }
 
 hipError_t launch_sweep(const sylt_plan_s &p, int op, int precision, void *X, hipStream_t s)
 {
+    if (p.diagT) {
+        if (precision == SYLT_FP64)
+            return op == SYLT_OP_N ? run_diag_sweep<double2, false>(p, static_cast<double2 *>(X), s)
+                                   : run_diag_sweep<double2, true>(p, static_cast<double2 *>(X), s);
+        return op == SYLT_OP_N ? run_diag_sweep<float2, false>(p, static_cast<float2 *>(X), s)
+                               : run_diag_sweep<float2, true>(p, static_cast<float2 *>(X), s);
+    }
     if (precision == SYLT_FP64) {
         return op == SYLT_OP_N ? run_sweep<double2, false>(p, static_cast<double2 *>(X), s)
                                : run_sweep<double2, true>(p, static_cast<double2 *>(X), s);

@@ -199,6 +199,14 @@ struct sylt_plan_s {
     std::vector<sylt::PassDesc> passes;   // transform passes (one LDS tile)
     std::vector<sylt::PassDesc> rpasses;  // residual passes (two LDS tiles)
     sylt::SweepPlan sweep;
+    // every T_k diagonal (all A_k normal, Remark 1): the sweep is the Hadamard
+    // product Y = Lambda o C, with the eigenvalue sum of entry p read from two
+    // tables of partial sums, dslo[p % dlo] (the low modes and the singleton
+    // scalars) + dshi[p / dlo] (the other modes)
+    bool diagT = false;
+    int dsplit = 0;                  // compressed modes of the low table
+    int64_t dlo = 1, dhi = 1;        // entries of the two tables
+    double2 *dslo = nullptr, *dshi = nullptr;
 };
 
 namespace sylt {
@@ -209,6 +217,8 @@ hipError_t launch_prepare_factors(const sylt_plan_s &p, hipStream_t s);
 hipError_t launch_separation(const sylt_plan_s &p, double *d_out, hipStream_t s);
 hipError_t launch_transform(const sylt_plan_s &p, int dir, int precision, void *X, hipStream_t s);
 hipError_t launch_sweep(const sylt_plan_s &p, int op, int precision, void *X, hipStream_t s);
+// the two partial-sum tables of the diagonal sweep (p.dslo, p.dshi)
+hipError_t launch_diag_tables(const sylt_plan_s &p, hipStream_t s);
 // R64 (complex128, may alias B) = B - sum_k A_k x_k X; if R32 != nullptr the
 // final pass also stores R as complex64.  Partial sums of |R|^2 and |B|^2 are
 // reduced into norms2_dev[0..1] (device).

@@ -239,7 +239,8 @@ def main():
     # is the headline roofline object
     tr_kernel = ("transform_mfma_kernel<double2,%d>" % n[0]
                  if all(v == n[0] for v in n) else "transform_pass_kernel")
-    sw_kernel = "sweep_tile_kernel<double2,false,%d>" % len([v for v in n if v > 1])
+    sw_kernel = "sweep_tile_kernel<double2,false,%d,%s>" % (
+        len([v for v in n if v > 1]), "true" if desc["sweep"]["local_solve"] == "pencil" else "false")
     roof_tr = roofline_entry(tr_kernel, tr_flops, tr_bytes * n_pass, t_tr, n_pass, True, w.name,
                              "paper_2412_15840_amd/csrc/transform.hip")
     roof_sw = roofline_entry(sw_kernel, sw_flops, sw_bytes, t_sw, n_lvl, False, w.name,
@@ -296,6 +297,24 @@ def main():
         log(f"evolve {evolve}")
         del Xe, ws_e
 
+    # ---------------------------------------------------------- normal A_k
+    # Remark 1: with normal A_k the plan's sweep is one Hadamard pass (read and
+    # write the tensor: 32 B per entry), timed at the same shape
+    normal = None
+    if not args.no_evolve:
+        An = [torch.from_numpy(a).cuda() for a in wl.normal_coefficient_matrices(w.n, w.seed)]
+        plan_n = sylt.Plan.factor(n, An)
+        if plan_n.describe()["sweep"]["diagonal"]:
+            Yn = Bd.clone()
+            t_n = time_events(lambda: sylt.sweep(plan_n, Yn, sylt.OP_N), reps, torch)
+            gbs = 32.0 * ntot / (t_n * 1e-3) / 1e9
+            normal = {"sweep_ms": round(t_n, 3), "gbs_alg": round(gbs, 1),
+                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                      "speedup_vs_tiled_sweep": round(t_sw / t_n, 2)}
+            del Yn
+        plan_n.destroy()
+        log(f"normal {normal}")
+
     # ---------------------------------------------------------- CPU oracle
     cpu = None
     if not args.no_cpu:
@@ -316,6 +335,7 @@ def main():
         "cpu_baseline": cpu,
         "solve_roofline": solve_roof,
         "phases": phases, "kernels": kernels, "mixed": mixed, "evolve": evolve,
+        "normal_sweep": normal,
         "plan": {"transform_passes": [p["extents"] for p in desc["transform_passes"]],
                  "sweep_block": desc["sweep"]["block"], "sweep_tile_levels": n_lvl,
                  "sep": desc["sep"]},

@@ -21,6 +21,9 @@ Recipe (the design doc states it too):
         from default_rng([seed, 1000 + c]) filling the interleaved (re, im)
         doubles of that chunk.
   W   (cotangent for the gradient workload) likewise with stream base 2000.
+  Normal A_k (normal-matrix fast path): Q_k diag(lambda_k) Q_k^* with Q_k the
+        unitary QR factor of a complex Gaussian matrix and lambda_k =
+        3 + N(0,1) + i N(0,1), from default_rng([seed, 100 + k]).
 """
 from __future__ import annotations
 
@@ -73,6 +76,20 @@ def coefficient_matrices(n, seed):
         g = np.random.default_rng([seed, k]).standard_normal((nk, nk))
         a = g / math.sqrt(nk) + 3.0 * np.eye(nk)
         out.append(a.astype(np.complex128))
+    return out
+
+
+def normal_coefficient_matrices(n, seed):
+    """Normal A_k = Q_k diag(lambda_k) Q_k^* (input recipe of the Remark 1 fast
+    path): Q_k the unitary factor of a complex Gaussian matrix, lambda_k =
+    3 + N(0,1) + i N(0,1), from default_rng([seed, 100 + k])."""
+    out = []
+    for k, nk in enumerate(n, start=1):
+        rng = np.random.default_rng([seed, 100 + k])
+        z = rng.standard_normal((nk, nk)) + 1j * rng.standard_normal((nk, nk))
+        q, _ = np.linalg.qr(z)
+        lam = 3.0 + rng.standard_normal(nk) + 1j * rng.standard_normal(nk)
+        out.append((q * lam) @ q.conj().T)
     return out
 
 

@@ -17,6 +17,7 @@ namespace {
 constexpr int kSchurIterPerN = 30;
 constexpr int64_t kTransformTileCap = 8192;  // complex entries per transform tile
 constexpr int64_t kResidualTileCap = 5120;   // two tiles (X and accumulator), 160 KB
+constexpr int64_t kResidualMfmaTileCap = 4096;  // two tiles and the A fragments, <= 160 KB
 
 int status_of(hipError_t e)
 {
@@ -128,6 +129,15 @@ void plan_passes(sylt_plan_s &p)
         }
     }
     plan_pass_list(p, kResidualTileCap, p.rpasses);
+    // the matrix-core residual passes: smaller tiles leave room for the A
+    // fragments; used when every pass has one extent of 8, 16 or 19
+    plan_pass_list(p, kResidualMfmaTileCap, p.mrpasses);
+    p.residual_mfma = !p.mrpasses.empty();
+    for (const PassDesc &pd : p.mrpasses) {
+        const int n = pd.uniform_n;
+        if ((n != 8 && n != 16 && n != 19) || residual_mfma_lds(pd) > std::min<size_t>(max_lds_bytes(), 160 * 1024))
+            p.residual_mfma = false;
+    }
 }
 
 size_t max_lds_bytes()
@@ -455,6 +465,7 @@ int init_plan(sylt_plan_s *p, int N, const int64_t *n)
     plan_passes(*p);
     int64_t maxt = 1;
     for (const PassDesc &pd : p->rpasses) maxt = std::max<int64_t>(maxt, pd.ntl * pd.ntr);
+    for (const PassDesc &pd : p->mrpasses) maxt = std::max<int64_t>(maxt, pd.ntl * pd.ntr);
     p->scratch_bytes = (size_t)(std::max<int64_t>(2 * maxt, 4096) + 64) * sizeof(double);
     SYLT_TRY(hipMalloc(&p->dScratch, p->scratch_bytes));
     return plan_sweep(*p);

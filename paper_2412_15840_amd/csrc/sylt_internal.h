@@ -198,6 +198,8 @@ struct sylt_plan_s {
     double sep = 0.0;
     std::vector<sylt::PassDesc> passes;   // transform passes (one LDS tile)
     std::vector<sylt::PassDesc> rpasses;  // residual passes (two LDS tiles)
+    std::vector<sylt::PassDesc> mrpasses; // residual passes of the matrix-core kernel
+    bool residual_mfma = false;           // every residual pass runs on the matrix cores
     sylt::SweepPlan sweep;
     // every T_k diagonal (all A_k normal, Remark 1): the sweep is the Hadamard
     // product Y = Lambda o C, with the eigenvalue sum of entry p read from two
@@ -225,6 +227,8 @@ hipError_t launch_diag_tables(const sylt_plan_s &p, hipStream_t s);
 hipError_t launch_residual(const sylt_plan_s &p, const double2 *B, const double2 *X, double2 *R64,
                            float2 *R32, double *norms2_dev, hipStream_t s);
 // the same with the matrices M_k of Mbuf (offsets p.moff) in place of A_k
+// LDS bytes of the matrix-core residual pass (two tiles and the A fragments)
+size_t residual_mfma_lds(const PassDesc &pa);
 hipError_t launch_residual_with(const sylt_plan_s &p, const double2 *Mbuf, const double2 *B,
                                 const double2 *X, double2 *R64, float2 *R32, double *norms2_dev,
                                 hipStream_t s);

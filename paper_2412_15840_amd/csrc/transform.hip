@@ -565,41 +565,15 @@ struct SingletonList {
     int64_t off[kMaxModes];  // offsets of the 1x1 A_k in the matrix buffer
 };
 
-template <int NN>
-__global__ void __launch_bounds__(kThreads) residual_pass_kernel(
-    const double2 *__restrict__ B, const double2 *__restrict__ X, double2 *R, float2 *R32,
-    const double2 *__restrict__ Abuf, PassDesc pa, SingletonList sing, int first, int last,
-    double *part_b, double *part_r)
+// R = src - acc on the tile (src = B in the first pass, R after), written as
+// complex128 (and complex64 in the last pass if R32); per-tile partial sums of
+// |B|^2 (first pass) and |R|^2 (last pass) in a fixed order.
+__device__ __forceinline__ void residual_finish(const double2 *__restrict__ B, double2 *R, float2 *R32,
+                                                const double2 *acc, const PassDesc &pa,
+                                                const TileCoord &tc, int first, int last,
+                                                double *part_b, double *part_r,
+                                                unsigned char *smem_raw)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double2 *xt = reinterpret_cast<double2 *>(smem_raw);
-    double2 *acc = xt + (int64_t)pa.lb * pa.G * pa.rb;
-    const TileCoord tc = tile_coord(pa);
-    load_tile<double2, double2>(xt, X, pa, tc);
-    __syncthreads();
-    double2 shift = make_double2(0.0, 0.0);
-    if (first)
-        for (int i = 0; i < sing.count; ++i) shift = cadd(shift, Abuf[sing.off[i]]);
-    const int total = pa.lb * (int)pa.G * pa.rb;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) acc[e] = cmul(shift, xt[e]);
-    __syncthreads();
-    for (int q = 0; q < pa.ng; ++q) {
-        const int n = NN > 0 ? NN : pa.gd[q];
-        const int nfib = pa.lb * (int)(pa.G / n) * tc.rbe;
-        const int stride = pa.lb * pa.gs[q];
-        const double2 *M = Abuf + pa.moff[q];
-        for (int f = threadIdx.x; f < nfib; f += blockDim.x) {
-            const int base = fibre_base(pa, tc, q, n, f);
-            if (base < 0) continue;
-            if constexpr (NN > 0)
-                fibre_fixed<double2, NN, true>(xt, acc, base, stride, M);
-            else if (n <= 24)
-                fibre_switch<double2, true>(xt, acc, base, stride, n, M);
-            else
-                fibre_generic<double2, true>(xt, acc, base, stride, n, M);
-        }
-        __syncthreads();
-    }
     // combine with the source and write; accumulate the norms
     double sb = 0.0, sr = 0.0;
     const double2 *src = first ? B : R;
@@ -644,6 +618,125 @@ __global__ void __launch_bounds__(kThreads) residual_pass_kernel(
         if (first) part_b[blockIdx.x] = tb;
         if (last) part_r[blockIdx.x] = trr;
     }
+}
+
+template <int NN>
+__global__ void __launch_bounds__(kThreads) residual_pass_kernel(
+    const double2 *__restrict__ B, const double2 *__restrict__ X, double2 *R, float2 *R32,
+    const double2 *__restrict__ Abuf, PassDesc pa, SingletonList sing, int first, int last,
+    double *part_b, double *part_r)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double2 *xt = reinterpret_cast<double2 *>(smem_raw);
+    double2 *acc = xt + (int64_t)pa.lb * pa.G * pa.rb;
+    const TileCoord tc = tile_coord(pa);
+    load_tile<double2, double2>(xt, X, pa, tc);
+    __syncthreads();
+    double2 shift = make_double2(0.0, 0.0);
+    if (first)
+        for (int i = 0; i < sing.count; ++i) shift = cadd(shift, Abuf[sing.off[i]]);
+    const int total = pa.lb * (int)pa.G * pa.rb;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) acc[e] = cmul(shift, xt[e]);
+    __syncthreads();
+    for (int q = 0; q < pa.ng; ++q) {
+        const int n = NN > 0 ? NN : pa.gd[q];
+        const int nfib = pa.lb * (int)(pa.G / n) * tc.rbe;
+        const int stride = pa.lb * pa.gs[q];
+        const double2 *M = Abuf + pa.moff[q];
+        for (int f = threadIdx.x; f < nfib; f += blockDim.x) {
+            const int base = fibre_base(pa, tc, q, n, f);
+            if (base < 0) continue;
+            if constexpr (NN > 0)
+                fibre_fixed<double2, NN, true>(xt, acc, base, stride, M);
+            else if (n <= 24)
+                fibre_switch<double2, true>(xt, acc, base, stride, n, M);
+            else
+                fibre_generic<double2, true>(xt, acc, base, stride, n, M);
+        }
+        __syncthreads();
+    }
+    residual_finish(B, R, R32, acc, pa, tc, first, last, part_b, part_r, smem_raw);
+}
+
+// The residual pass on the matrix cores (extents 8, 16 or 19 in the pass):
+// the X tile stays in LDS and every mode's product M_q x_q X, formed by the
+// same real-ified 16x16x4 MFMA GEMM as the transform pass, is added into an
+// LDS accumulator tile instead of overwriting the fibres.
+template <int NN>
+__global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
+    const double2 *__restrict__ B, const double2 *__restrict__ X, double2 *R, float2 *R32,
+    const double2 *__restrict__ Abuf, PassDesc pa, SingletonList sing, int first, int last,
+    double *part_b, double *part_r)
+{
+    using MT = MfmaT<double>;
+    constexpr int RB = (2 * NN + 15) / 16;
+    constexpr int KS = (2 * NN + 3) / 4;
+    constexpr int WAVES = kMfmaThreads / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int total = pa.lb * (int)pa.G * pa.rb;
+    double2 *xt = reinterpret_cast<double2 *>(smem_raw);
+    double2 *acc = xt + total;
+    double *afr = reinterpret_cast<double *>(acc + total);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const TileCoord tc = tile_coord(pa);
+    for (int idx = threadIdx.x; idx < pa.ng * RB * KS * 64; idx += kMfmaThreads) {
+        const int l = idx & 63;
+        const int frag = idx >> 6;
+        const int kk = frag % KS, rb = (frag / KS) % RB, q = frag / (KS * RB);
+        const int row = 16 * rb + (l & 15), k = 4 * kk + (l >> 4);
+        const int i = row >> 1, m = k >> 1;
+        double v = 0.0;
+        if (i < NN && m < NN) {
+            const double2 c = Abuf[pa.moff[q] + i + NN * m];
+            const int a = row & 1, b = k & 1;
+            v = a == b ? c.x : (a ? c.y : -c.y);
+        }
+        afr[idx] = v;
+    }
+    load_tile<double2, double2>(xt, X, pa, tc);
+    __syncthreads();
+    double2 shift = make_double2(0.0, 0.0);
+    if (first)
+        for (int i = 0; i < sing.count; ++i) shift = cadd(shift, Abuf[sing.off[i]]);
+    for (int e = threadIdx.x; e < total; e += kMfmaThreads) acc[e] = cmul(shift, xt[e]);
+    __syncthreads();
+    const double *tr = reinterpret_cast<const double *>(xt);
+    double *ar = reinterpret_cast<double *>(acc);
+    for (int q = 0; q < pa.ng; ++q) {
+        const double *aq = afr + q * RB * KS * 64 + lane;
+        const int nfib = pa.lb * (int)(pa.G / NN) * tc.rbe;
+        const int stride = pa.lb * pa.gs[q];
+        const int ngroups = (nfib + 15) >> 4;
+        for (int grp = wave; grp < ngroups; grp += WAVES) {
+            const int f = 16 * grp + (lane & 15);
+            const int base = f < nfib ? fibre_base(pa, tc, q, NN, f) : -1;
+            const int kb = lane >> 4;
+            typename MT::acc d[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) d[rb] = typename MT::acc{0, 0, 0, 0};
+#pragma unroll 2
+            for (int kk = 0; kk < KS; ++kk) {
+                const int k = 4 * kk + kb;
+                const int m = k >> 1;
+                const double b = (base >= 0 && m < NN) ? tr[2 * (base + m * stride) + (k & 1)] : 0.0;
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) d[rb] = MT::mma(aq[(rb * KS + kk) * 64], b, d[rb]);
+            }
+            if (base >= 0) {
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 16 * rb + MT::row(lane, v);
+                        const int i = row >> 1;
+                        if (i < NN) ar[2 * (base + i * stride) + (row & 1)] += d[rb][v];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    residual_finish(B, R, R32, acc, pa, tc, first, last, part_b, part_r, smem_raw);
 }
 
 __global__ void reduce_sum_kernel(const double *__restrict__ in, int64_t n, double *out)
@@ -778,6 +871,13 @@ hipError_t launch_transform(const sylt_plan_s &p, int dir, int precision, void *
     return hipSuccess;
 }
 
+size_t residual_mfma_lds(const PassDesc &pa)
+{
+    const int n = pa.uniform_n;
+    const size_t frags = (size_t)pa.ng * ((2 * n + 15) / 16) * ((2 * n + 3) / 4) * 64;
+    return pa.lds_bytes(sizeof(double2)) * 2 + frags * sizeof(double);
+}
+
 hipError_t launch_transform_with(const sylt_plan_s &p, const double2 *M, double2 *X, hipStream_t s)
 {
     for (const PassDesc &pa : p.passes) {
@@ -797,10 +897,11 @@ hipError_t launch_residual_with(const sylt_plan_s &p, const double2 *Mbuf, const
                                 const double2 *X, double2 *R64, float2 *R32, double *norms2_dev,
                                 hipStream_t s)
 {
-    const int P = (int)p.rpasses.size();
+    const std::vector<PassDesc> &passes = p.residual_mfma ? p.mrpasses : p.rpasses;
+    const int P = (int)passes.size();
     // plan scratch: [part_b (max tiles)] [part_r (max tiles)]
     int64_t maxt = 1;
-    for (const PassDesc &pa : p.rpasses) maxt = std::max<int64_t>(maxt, pa.ntl * pa.ntr);
+    for (const PassDesc &pa : passes) maxt = std::max<int64_t>(maxt, pa.ntl * pa.ntr);
     double *part_b = p.dScratch;
     double *part_r = p.dScratch + maxt;
     if (P == 0) return hipErrorInvalidValue;  // all modes singleton: not supported here
@@ -808,11 +909,38 @@ hipError_t launch_residual_with(const sylt_plan_s &p, const double2 *Mbuf, const
     for (int k = 0; k < p.N; ++k)
         if (p.n[k] == 1) sing.off[sing.count++] = p.moff[k];
     for (int i = 0; i < P; ++i) {
-        const PassDesc &pa = p.rpasses[i];
+        const PassDesc &pa = passes[i];
         const int64_t tiles = pa.ntl * pa.ntr;
         const size_t lds = std::max<size_t>(pa.lds_bytes(sizeof(double2)) * 2, 64);
         const int first = i == 0, last = i == P - 1;
         hipError_t e;
+        if (p.residual_mfma) {
+#define SYLT_MRLAUNCH(NNV)                                                                        \
+    do {                                                                                          \
+        const size_t mlds = residual_mfma_lds(pa);                                                \
+        e = allow_lds(residual_mfma_kernel<NNV>, mlds);                                           \
+        if (e != hipSuccess) return e;                                                            \
+        hipLaunchKernelGGL(residual_mfma_kernel<NNV>, dim3((unsigned)tiles), dim3(kMfmaThreads),  \
+                           mlds, s, B, X, R64, last ? R32 : nullptr, Mbuf, pa, sing, first, last, \
+                           part_b, part_r);                                                       \
+    } while (0)
+            switch (pa.uniform_n) {
+                case 8: SYLT_MRLAUNCH(8); break;
+                case 16: SYLT_MRLAUNCH(16); break;
+                case 19: SYLT_MRLAUNCH(19); break;
+                default: return hipErrorInvalidValue;
+            }
+#undef SYLT_MRLAUNCH
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            if (first && norms2_dev)
+                hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(kThreads), 0, s, part_b, tiles,
+                                   norms2_dev + 1);
+            if (last && norms2_dev)
+                hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(kThreads), 0, s, part_r, tiles,
+                                   norms2_dev + 0);
+            continue;
+        }
 #define SYLT_RLAUNCH(KER)                                                                       \
     do {                                                                                        \
         e = allow_lds(KER, lds);                                                                \

@@ -9,7 +9,8 @@ tensor); inputs are seeded synthetic tensors already resident in HBM when the
 timed region starts.  The mixed-precision solve (FP32 transforms, FP64 sweep,
 FP64 residual, iterative refinement to a 1e-12 relative residual) is timed on
 the same inputs and reported beside it, and so is the time evolution of
-Theorem 1 (sylt_evolve at t = 0.1).
+Theorem 1 (sylt_evolve at t = 0.1), the sweep of a plan with normal A_k
+(Remark 1), and the advection-diffusion example of Section 5.3.
 
 Prints ONE JSON line (rank 0).  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload C3b]
@@ -315,6 +316,30 @@ def main():
         plan_n.destroy()
         log(f"normal {normal}")
 
+    # ---------------------------------------------------------- Section 5.3
+    # the advection-diffusion example at the paper's size (N = 6, 16 Hermite
+    # nodes per axis, t = 1): plan (device Schur) + sylt_evolve, and the max
+    # error against the exact solution (1 + e^t) exp(-x.x)
+    advdif = None
+    if not args.no_evolve:
+        xh, Ah, Bh6, X0h = wl.advection_diffusion(6)
+        A6 = [torch.from_numpy(a).cuda() for a in Ah]
+        B6, X06 = torch.from_numpy(Bh6).cuda(), torch.from_numpy(X0h).cuda()
+        X6 = torch.empty_like(B6)
+
+        def advdif_run():
+            p6 = sylt.Plan.factor([16] * 6, A6)
+            sylt.evolve(p6, 1.0, B6, X06, out=X6)
+            return p6
+
+        advdif_run().destroy()
+        torch.cuda.synchronize()
+        t_a = time_events(lambda: advdif_run().destroy(), 3, torch)
+        err = float(np.max(np.abs(X6.cpu().numpy() - wl.advection_diffusion_exact(xh, 6, 1.0))))
+        advdif = {"N": 6, "nodes": 16, "t": 1.0, "ms": round(t_a, 3), "max_error_vs_exact": err,
+                  "paper_matlab_s": 25.73, "paper_max_error": 9.6811e-14}
+        log(f"advection-diffusion {advdif}")
+
     # ---------------------------------------------------------- CPU oracle
     cpu = None
     if not args.no_cpu:
@@ -335,7 +360,7 @@ def main():
         "cpu_baseline": cpu,
         "solve_roofline": solve_roof,
         "phases": phases, "kernels": kernels, "mixed": mixed, "evolve": evolve,
-        "normal_sweep": normal,
+        "normal_sweep": normal, "advection_diffusion": advdif,
         "plan": {"transform_passes": [p["extents"] for p in desc["transform_passes"]],
                  "sweep_block": desc["sweep"]["block"], "sweep_tile_levels": n_lvl,
                  "sep": desc["sep"]},

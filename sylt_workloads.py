@@ -93,6 +93,59 @@ def normal_coefficient_matrices(n, seed):
     return out
 
 
+def hermite_differentiation(m, b):
+    """Nodes and first/second derivative matrices of Hermite-function
+    interpolation (the discretisation of the advection-diffusion example,
+    Section 5.3): nodes x = r / b with r the m roots of the Hermite polynomial
+    H_m; u(x) ~ sum_j u_j a(x) l_j(x) / a(x_j) with the Lagrange basis l_j of
+    the nodes and the weight a = exp(-(b x)^2 / 2).  Built from the barycentric
+    Lagrange derivatives L1, L2 (Berrut & Trefethen 2004) in the variable r:
+        D1 = A L1 A^-1 + diag(a'/a),
+        D2 = A L2 A^-1 + 2 diag(a'/a) A L1 A^-1 + diag(a''/a),
+    with A = diag(a), a'/a = -r, a''/a = r^2 - 1, then scaled by b and b^2."""
+    r = np.sort(np.polynomial.hermite.hermroots([0] * m + [1]).real)
+    d = r[:, None] - r[None, :]
+    np.fill_diagonal(d, 1.0)
+    w = 1.0 / np.prod(d, axis=1)                 # barycentric weights
+    inv = 1.0 / d
+    np.fill_diagonal(inv, 0.0)
+    L1 = (w[None, :] / w[:, None]) * inv
+    np.fill_diagonal(L1, 0.0)
+    np.fill_diagonal(L1, -L1.sum(axis=1))
+    L2 = 2.0 * L1 * (np.diag(L1)[:, None] - inv)
+    np.fill_diagonal(L2, 0.0)
+    np.fill_diagonal(L2, -L2.sum(axis=1))
+    a = np.exp(-r * r / 2.0)
+    S1 = a[:, None] * L1 / a[None, :]
+    S2 = a[:, None] * L2 / a[None, :]
+    D1 = S1 + np.diag(-r)
+    D2 = S2 + 2.0 * np.diag(-r) @ S1 + np.diag(r * r - 1.0)
+    return r / b, b * D1, b * b * D2
+
+
+def advection_diffusion(N, m=16, b=1.4):
+    """The advection-diffusion example of Section 5.3 on m Hermite nodes per
+    axis: u_t = Lap u + 2 x.grad u + (2N+1) u - exp(-x.x), u(x,0) = 2 exp(-x.x),
+    exact solution (1 + e^t) exp(-x.x).  Returns (x, [A]*N, B, X0) with
+    A = D2 + 2 diag(x) D1 + (2N+1)/N I and flat column-major B, X0."""
+    x, D1, D2 = hermite_differentiation(m, b)
+    A = (D2 + 2.0 * np.diag(x) @ D1 + (2.0 * N + 1.0) / N * np.eye(m)).astype(np.complex128)
+    g = np.exp(-x * x)
+    G = g
+    for _ in range(N - 1):
+        G = np.multiply.outer(G, g)
+    G = np.asarray(G).ravel(order="F")
+    return x, [A] * N, (-G).astype(np.complex128), (2.0 * G).astype(np.complex128)
+
+
+def advection_diffusion_exact(x, N, t):
+    g = np.exp(-x * x)
+    G = g
+    for _ in range(N - 1):
+        G = np.multiply.outer(G, g)
+    return (1.0 + math.exp(t)) * np.asarray(G).ravel(order="F")
+
+
 def _fill_chunk(buf_f64, c, seed, stream, nchunks_total):
     rng = np.random.default_rng([seed, stream + c])
     rng.standard_normal(out=buf_f64)

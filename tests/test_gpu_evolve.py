@@ -94,3 +94,26 @@ def test_evolve_rejects_bad_arguments():
     with pytest.raises(sylt.SyltError) as e:
         sylt.evolve(plan, 0.1, B, X0, workspace=small)
     assert e.value.code == -7
+
+
+def test_advection_diffusion_N6_matches_the_exact_solution():
+    # Section 5.3 at the paper's size: N = 6, 16 Hermite nodes per axis, t = 1
+    # (the paper reports a max error of 9.7e-14 against the exact solution)
+    import sylt_workloads as wl
+    sylt = _sylt()
+    N = 6
+    banner("advection-diffusion N=6 m=16 t=1")
+    x, A, B, X0 = wl.advection_diffusion(N)
+    plan = sylt.Plan.factor([16] * N, [dev(a) for a in A])
+    X = host(sylt.evolve(plan, 1.0, dev(B), dev(X0)))
+    exact = wl.advection_diffusion_exact(x, N, 1.0)
+    assert np.max(np.abs(X - exact)) <= 1e-12
+
+
+def test_advection_diffusion_N3_matches_oracle():
+    import sylt_workloads as wl
+    N = 3
+    x, A, B, X0 = wl.advection_diffusion(N)
+    ref = oracle.evolve((16,) * N, A, B, X0, 1.0)
+    got = _gpu_evolve((16,) * N, A, B, X0, 1.0)
+    assert relmax(got, ref) <= TOL

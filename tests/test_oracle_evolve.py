@@ -1,14 +1,17 @@
 """Pins of the oracle's Theorem 1 (time evolution) against facts that do not
 go through it: the closed-form solution of the linear ODE with the dense
 Kronecker-sum matrix, fourth-order Runge-Kutta integration (the paper's own
-check in its Section 4), the initial condition, and the ODE itself by central
-differences in t.  CPU only.
+check in Section 5.2), the initial condition, the ODE itself by central
+differences in t, and the exact solution of the advection-diffusion example
+of Section 5.3 (with the Hermite differentiation matrices checked as the paper
+checks them).  CPU only.
 """
 import numpy as np
 import pytest
 import scipy.linalg
 
 import oracle
+import sylt_workloads as wl
 from dense_forms import crandn, kron_sum, random_matrix
 
 
@@ -68,3 +71,20 @@ def test_evolve_satisfies_the_ode():
     d = (oracle.evolve(n, A, b, x0, t + h) - oracle.evolve(n, A, b, x0, t - h)) / (2 * h)
     rhs = oracle.apply(n, A, oracle.evolve(n, A, b, x0, t)) + b
     assert np.max(np.abs(d - rhs)) <= 1e-6 * np.max(np.abs(rhs))
+
+
+def test_hermite_differentiation_matches_the_papers_check():
+    # Section 5.3: D1 and D2 on m = 16 nodes with scale 1.4 applied to exp(-x^2)
+    # (the paper reports 1.2e-15 and 1.5e-14 in the max norm)
+    x, D1, D2 = wl.hermite_differentiation(16, 1.4)
+    g = np.exp(-x * x)
+    assert np.max(np.abs(D1 @ g + 2 * x * g)) <= 1e-13
+    assert np.max(np.abs(D2 @ g - (4 * x * x - 2) * g)) <= 1e-12
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_evolve_advection_diffusion_exact_solution(N):
+    # Section 5.3: u(x, t) = (1 + e^t) exp(-x.x) at t = 1
+    x, A, B, X0 = wl.advection_diffusion(N)
+    X = oracle.evolve((16,) * N, A, B, X0, 1.0)
+    assert np.max(np.abs(X - wl.advection_diffusion_exact(x, N, 1.0))) <= 1e-12

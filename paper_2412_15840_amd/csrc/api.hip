@@ -17,7 +17,7 @@ namespace {
 constexpr int kSchurIterPerN = 30;
 constexpr int64_t kTransformTileCap = 8192;  // complex entries per transform tile
 constexpr int64_t kResidualTileCap = 5120;   // two tiles (X and accumulator), 160 KB
-constexpr int64_t kResidualMfmaTileCap = 4096;  // two tiles and the A fragments, <= 160 KB
+constexpr int64_t kResidualMfmaTileCap = kResidualMfmaCap;  // two tiles and the A fragments, <= 160 KB
 
 int status_of(hipError_t e)
 {

@@ -20,6 +20,7 @@ constexpr int kSweepThreads = 1024;   // lanes of a sweep workgroup
 constexpr int kSweepMaxRounds = 32;   // local-solve rounds held per lane in registers
 constexpr int kSweepPencilMax = 20;   // longest mode-0 pencil held in one lane's registers
 constexpr int kSweepPencilModes = 8;  // most tiled modes of the pencil form
+constexpr int kResidualMfmaCap = 4096;  // tile entries of the matrix-core residual pass
 
 // ----------------------------------------------------------------- complex
 // double2 / float2 hold (re, im).  All products are written as explicit fused

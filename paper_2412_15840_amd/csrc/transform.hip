@@ -571,7 +571,7 @@ struct SingletonList {
 __device__ __forceinline__ void residual_finish(const double2 *__restrict__ B, double2 *R, float2 *R32,
                                                 const double2 *acc, const PassDesc &pa,
                                                 const TileCoord &tc, int first, int last,
-                                                double *part_b, double *part_r,
+                                                double *part_b, double *part_r, int64_t tile,
                                                 unsigned char *smem_raw)
 {
     // combine with the source and write; accumulate the norms
@@ -615,8 +615,8 @@ __device__ __forceinline__ void residual_finish(const double2 *__restrict__ B, d
             tb += red[2 * w];
             trr += red[2 * w + 1];
         }
-        if (first) part_b[blockIdx.x] = tb;
-        if (last) part_r[blockIdx.x] = trr;
+        if (first) part_b[tile] = tb;
+        if (last) part_r[tile] = trr;
     }
 }
 
@@ -655,8 +655,10 @@ __global__ void __launch_bounds__(kThreads) residual_pass_kernel(
         }
         __syncthreads();
     }
-    residual_finish(B, R, R32, acc, pa, tc, first, last, part_b, part_r, smem_raw);
+    residual_finish(B, R, R32, acc, pa, tc, first, last, part_b, part_r, blockIdx.x, smem_raw);
 }
+
+constexpr int kResidualRegs = kResidualMfmaCap / kMfmaThreads;  // X entries per lane of a tile
 
 // The residual pass on the matrix cores (extents 8, 16 or 19 in the pass):
 // the X tile stays in LDS and every mode's product M_q x_q X, formed by the
@@ -678,7 +680,6 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
     double2 *acc = xt + total;
     double *afr = reinterpret_cast<double *>(acc + total);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const TileCoord tc = tile_coord(pa);
     for (int idx = threadIdx.x; idx < pa.ng * RB * KS * 64; idx += kMfmaThreads) {
         const int l = idx & 63;
         const int frag = idx >> 6;
@@ -693,50 +694,87 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
         }
         afr[idx] = v;
     }
-    load_tile<double2, double2>(xt, X, pa, tc);
-    __syncthreads();
     double2 shift = make_double2(0.0, 0.0);
     if (first)
         for (int i = 0; i < sing.count; ++i) shift = cadd(shift, Abuf[sing.off[i]]);
-    for (int e = threadIdx.x; e < total; e += kMfmaThreads) acc[e] = cmul(shift, xt[e]);
-    __syncthreads();
-    const double *tr = reinterpret_cast<const double *>(xt);
-    double *ar = reinterpret_cast<double *>(acc);
-    for (int q = 0; q < pa.ng; ++q) {
-        const double *aq = afr + q * RB * KS * 64 + lane;
-        const int nfib = pa.lb * (int)(pa.G / NN) * tc.rbe;
-        const int stride = pa.lb * pa.gs[q];
-        const int ngroups = (nfib + 15) >> 4;
-        for (int grp = wave; grp < ngroups; grp += WAVES) {
-            const int f = 16 * grp + (lane & 15);
-            const int base = f < nfib ? fibre_base(pa, tc, q, NN, f) : -1;
-            const int kb = lane >> 4;
-            typename MT::acc d[RB];
+    // persistent: tiles blockIdx.x, blockIdx.x + gridDim.x, ...; the X entries
+    // of the next tile are loaded into registers while this one is multiplied
+    const int64_t ntiles = pa.ntl * pa.ntr;
+    int64_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    double pre_re[kResidualRegs], pre_im[kResidualRegs];
+    auto load_regs = [&](const TileCoord &c) {
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) d[rb] = typename MT::acc{0, 0, 0, 0};
-#pragma unroll 2
-            for (int kk = 0; kk < KS; ++kk) {
-                const int k = 4 * kk + kb;
-                const int m = k >> 1;
-                const double b = (base >= 0 && m < NN) ? tr[2 * (base + m * stride) + (k & 1)] : 0.0;
-#pragma unroll
-                for (int rb = 0; rb < RB; ++rb) d[rb] = MT::mma(aq[(rb * KS + kk) * 64], b, d[rb]);
+        for (int i = 0; i < kResidualRegs; ++i) {
+            const int e = threadIdx.x + i * kMfmaThreads;
+            const int l = e & (pa.lb - 1);
+            const int rest = e >> pa.lbshift;
+            const int g = rest % (int)pa.G, r = rest / (int)pa.G;
+            if (e < total && l < c.lbe && r < c.rbe) {
+                const double2 v = X[c.l0 + l + pa.Lin * (g + pa.G * (c.r0 + r))];
+                pre_re[i] = v.x;
+                pre_im[i] = v.y;
             }
-            if (base >= 0) {
+        }
+    };
+    TileCoord tc = tile_coord_of(pa, t);
+    load_regs(tc);
+    while (true) {
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int row = 16 * rb + MT::row(lane, v);
-                        const int i = row >> 1;
-                        if (i < NN) ar[2 * (base + i * stride) + (row & 1)] += d[rb][v];
-                    }
-                }
+        for (int i = 0; i < kResidualRegs; ++i) {
+            const int e = threadIdx.x + i * kMfmaThreads;
+            if (e < total) {
+                const double2 x = make_double2(pre_re[i], pre_im[i]);
+                xt[e] = x;
+                acc[e] = cmul(shift, x);
             }
         }
         __syncthreads();
+        const int64_t tn = t + gridDim.x;
+        const TileCoord tcn = tile_coord_of(pa, tn < ntiles ? tn : t);
+        if (tn < ntiles) load_regs(tcn);
+        const double *tr = reinterpret_cast<const double *>(xt);
+        double *ar = reinterpret_cast<double *>(acc);
+        for (int q = 0; q < pa.ng; ++q) {
+            const double *aq = afr + q * RB * KS * 64 + lane;
+            const int nfib = pa.lb * (int)(pa.G / NN) * tc.rbe;
+            const int stride = pa.lb * pa.gs[q];
+            const int ngroups = (nfib + 15) >> 4;
+            for (int grp = wave; grp < ngroups; grp += WAVES) {
+                const int f = 16 * grp + (lane & 15);
+                const int base = f < nfib ? fibre_base(pa, tc, q, NN, f) : -1;
+                const int kb = lane >> 4;
+                typename MT::acc d[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) d[rb] = typename MT::acc{0, 0, 0, 0};
+#pragma unroll 2
+                for (int kk = 0; kk < KS; ++kk) {
+                    const int k = 4 * kk + kb;
+                    const int m = k >> 1;
+                    const double b = (base >= 0 && m < NN) ? tr[2 * (base + m * stride) + (k & 1)] : 0.0;
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) d[rb] = MT::mma(aq[(rb * KS + kk) * 64], b, d[rb]);
+                }
+                if (base >= 0) {
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int row = 16 * rb + MT::row(lane, v);
+                            const int i = row >> 1;
+                            if (i < NN) ar[2 * (base + i * stride) + (row & 1)] += d[rb][v];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        residual_finish(B, R, R32, acc, pa, tc, first, last, part_b, part_r, t, smem_raw);
+        if (tn >= ntiles) break;
+        __syncthreads();
+        t = tn;
+        tc = tcn;
     }
-    residual_finish(B, R, R32, acc, pa, tc, first, last, part_b, part_r, smem_raw);
 }
 
 __global__ void reduce_sum_kernel(const double *__restrict__ in, int64_t n, double *out)
@@ -753,6 +791,15 @@ __global__ void reduce_sum_kernel(const double *__restrict__ in, int64_t n, doub
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
         *out = t;
     }
+}
+
+int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    return cus;
 }
 
 template <typename K>
@@ -920,7 +967,13 @@ hipError_t launch_residual_with(const sylt_plan_s &p, const double2 *Mbuf, const
         const size_t mlds = residual_mfma_lds(pa);                                                \
         e = allow_lds(residual_mfma_kernel<NNV>, mlds);                                           \
         if (e != hipSuccess) return e;                                                            \
-        hipLaunchKernelGGL(residual_mfma_kernel<NNV>, dim3((unsigned)tiles), dim3(kMfmaThreads),  \
+        int occ = 1;                                                                              \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, residual_mfma_kernel<NNV>,         \
+                                                         kMfmaThreads, mlds) != hipSuccess ||     \
+            occ < 1)                                                                              \
+            occ = 1;                                                                              \
+        const int64_t grid = std::min<int64_t>(tiles, (int64_t)device_cus() * occ);              \
+        hipLaunchKernelGGL(residual_mfma_kernel<NNV>, dim3((unsigned)grid), dim3(kMfmaThreads),   \
                            mlds, s, B, X, R64, last ? R32 : nullptr, Mbuf, pa, sing, first, last, \
                            part_b, part_r);                                                       \
     } while (0)

@@ -276,48 +276,63 @@ int plan_sweep(sylt_plan_s &p)
         std::vector<int> fill(lloff.begin(), lloff.end() - 1);
         for (int64_t t = 0; t < S; ++t) llist[fill[lev[t]]++] = (int)t;
     }
-    // tiles sorted by block-index sum
+    // tiles ordered by block-index sum (tile level) and, within a level, in
+    // Z-order (bit-interleaved block indices): consecutive tiles are
+    // neighbours in every mode, so they share pull sources.  A mixed-radix
+    // counter gives every tile id its level and Z key without divisions, and
+    // an LSD radix sort orders the ids by (level, key).
     std::vector<int> tlev(ntiles);
+    std::vector<uint64_t> key(ntiles, 0);
     sp.level_off.assign(nlev + 1, 0);
-    for (int64_t id = 0; id < ntiles; ++id) {
-        int64_t rem = id;
-        int l = 0;
-        for (int j = 0; j < M; ++j) {
-            l += (int)(rem % sd.nb[j]);
-            rem /= sd.nb[j];
-        }
-        tlev[id] = l;
-        sp.level_off[l + 1]++;
-    }
-    for (int l = 0; l < nlev; ++l) sp.level_off[l + 1] += sp.level_off[l];
-    std::vector<int> tiles(ntiles);
-    {
-        std::vector<int64_t> fill(sp.level_off.begin(), sp.level_off.end() - 1);
-        for (int64_t id = 0; id < ntiles; ++id) tiles[fill[tlev[id]]++] = (int)id;
-    }
-    // within a level, Z-order (bit-interleaved block indices): consecutive
-    // tiles are neighbours in every mode, so they share pull sources
+    int kbits = 0;
     {
         int maxnb = 1;
         for (int j = 0; j < M; ++j) maxnb = std::max(maxnb, sd.nb[j]);
         const int bits = std::max(1, ilog2(maxnb));
-        if (M * bits <= 64) {  // otherwise keep the id order
-            std::vector<uint64_t> key(ntiles);
-            for (int64_t id = 0; id < ntiles; ++id) {
-                int64_t rem = id;
-                uint64_t k = 0;
-                for (int j = 0; j < M; ++j) {
-                    const uint64_t P = (uint64_t)(rem % sd.nb[j]);
-                    rem /= sd.nb[j];
+        if (M * bits <= 64) kbits = M * bits;  // otherwise keep the id order in a level
+        std::vector<std::vector<uint64_t>> spread(M);
+        for (int j = 0; j < M; ++j) {
+            spread[j].assign(sd.nb[j], 0);
+            if (kbits)
+                for (int P = 0; P < sd.nb[j]; ++P)
                     for (int bit = 0; bit < bits; ++bit)
-                        k |= ((P >> bit) & 1ull) << (bit * M + j);
-                }
-                key[id] = k;
-            }
-            for (int l = 0; l < nlev; ++l)
-                std::sort(tiles.begin() + sp.level_off[l], tiles.begin() + sp.level_off[l + 1],
-                          [&](int a, int b) { return key[a] < key[b]; });
+                        spread[j][P] |= (((uint64_t)P >> bit) & 1ull) << (bit * M + j);
         }
+        std::vector<int> dig(M, 0);
+        int l = 0;
+        uint64_t k = 0;
+        for (int64_t id = 0; id < ntiles; ++id) {
+            tlev[id] = l;
+            key[id] = k;
+            sp.level_off[l + 1]++;
+            for (int j = 0; j < M; ++j) {  // next id: increment the mixed-radix digits
+                k -= spread[j][dig[j]];
+                l -= dig[j];
+                if (++dig[j] < sd.nb[j]) {
+                    k += spread[j][dig[j]];
+                    l += dig[j];
+                    break;
+                }
+                dig[j] = 0;
+            }
+        }
+    }
+    for (int l = 0; l < nlev; ++l) sp.level_off[l + 1] += sp.level_off[l];
+    std::vector<int> tiles(ntiles);
+    {
+        std::vector<int> order(ntiles), tmp(ntiles);
+        for (int64_t id = 0; id < ntiles; ++id) order[id] = (int)id;
+        constexpr int kDigit = 11;
+        for (int shift = 0; shift < kbits; shift += kDigit) {
+            std::vector<int64_t> cnt((1 << kDigit) + 1, 0);
+            for (int64_t i = 0; i < ntiles; ++i) cnt[((key[order[i]] >> shift) & ((1 << kDigit) - 1)) + 1]++;
+            for (int d = 0; d < (1 << kDigit); ++d) cnt[d + 1] += cnt[d];
+            for (int64_t i = 0; i < ntiles; ++i)
+                tmp[cnt[(key[order[i]] >> shift) & ((1 << kDigit) - 1)]++] = order[i];
+            order.swap(tmp);
+        }
+        std::vector<int64_t> fill(sp.level_off.begin(), sp.level_off.end() - 1);
+        for (int64_t i = 0; i < ntiles; ++i) tiles[fill[tlev[order[i]]]++] = order[i];
     }
     // per-lane packed local-solve work (one 32-bit word per lane and round)
     std::vector<int> lanetab(1, -1);

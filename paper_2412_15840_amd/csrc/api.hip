@@ -755,8 +755,7 @@ int sylt_solve(sylt_plan p, const sylt_opts *o, const double *B, double *X, void
         info->sep = p->sep;
     }
     if (precision == SYLT_FP64) {
-        if (Xc != Bc) SYLT_TRY(launch_copy_c128(Xc, Bc, p->ntot, s));
-        SYLT_TRY(launch_transform(*p, SYLT_TO_SCHUR, SYLT_FP64, Xc, s));
+        SYLT_TRY(launch_transform_from(*p, SYLT_TO_SCHUR, Bc, Xc, s));
         SYLT_TRY(launch_sweep(*p, SYLT_OP_N, SYLT_FP64, Xc, s));
         SYLT_TRY(launch_transform(*p, SYLT_FROM_SCHUR, SYLT_FP64, Xc, s));
         if (info) {
@@ -824,11 +823,9 @@ int sylt_evolve(sylt_plan p, double t, const double *B, const double *X0, double
     double2 *W = C + n;
     SYLT_TRY(launch_expm(*p, t, s));
     // C = U^*-chain(B) first, so that X may alias B
-    SYLT_TRY(launch_copy_c128(C, reinterpret_cast<const double2 *>(B), n, s));
-    SYLT_TRY(launch_transform(*p, SYLT_TO_SCHUR, SYLT_FP64, C, s));
+    SYLT_TRY(launch_transform_from(*p, SYLT_TO_SCHUR, reinterpret_cast<const double2 *>(B), C, s));
     // Y(0) = U^*-chain(X0), held in X
-    if (X != X0) SYLT_TRY(launch_copy_c128(Xc, reinterpret_cast<const double2 *>(X0), n, s));
-    SYLT_TRY(launch_transform(*p, SYLT_TO_SCHUR, SYLT_FP64, Xc, s));
+    SYLT_TRY(launch_transform_from(*p, SYLT_TO_SCHUR, reinterpret_cast<const double2 *>(X0), Xc, s));
     // W = sum_k T_k x_k Y(0) + C, as C - sum_k (-T_k) x_k Y(0)
     if (!p->rpasses.empty())
         SYLT_TRY(launch_residual_with(*p, p->dTneg, C, Xc, W, nullptr, nullptr, s));
@@ -849,8 +846,7 @@ int sylt_solve_backward(sylt_plan p, const double *X, const double *GX, double *
     if (!p || !X || !GX || !GB) return SYLT_E_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     double2 *G = reinterpret_cast<double2 *>(GB);
-    if (GB != GX) SYLT_TRY(launch_copy_c128(G, reinterpret_cast<const double2 *>(GX), p->ntot, s));
-    SYLT_TRY(launch_transform(*p, SYLT_TO_SCHUR, SYLT_FP64, G, s));
+    SYLT_TRY(launch_transform_from(*p, SYLT_TO_SCHUR, reinterpret_cast<const double2 *>(GX), G, s));
     SYLT_TRY(launch_sweep(*p, SYLT_OP_C, SYLT_FP64, G, s));
     SYLT_TRY(launch_transform(*p, SYLT_FROM_SCHUR, SYLT_FP64, G, s));
     if (GA) {

@@ -219,6 +219,10 @@ hipError_t launch_schur(const sylt_plan_s &p, int max_iter_per_n, hipStream_t s)
 hipError_t launch_prepare_factors(const sylt_plan_s &p, hipStream_t s);
 hipError_t launch_separation(const sylt_plan_s &p, double *d_out, hipStream_t s);
 hipError_t launch_transform(const sylt_plan_s &p, int dir, int precision, void *X, hipStream_t s);
+// FP64 chain whose first pass reads src and writes X (out of place; later
+// passes in place): the copy of src into X is folded into the first pass
+hipError_t launch_transform_from(const sylt_plan_s &p, int dir, const double2 *src, double2 *X,
+                                 hipStream_t s);
 hipError_t launch_sweep(const sylt_plan_s &p, int op, int precision, void *X, hipStream_t s);
 // the two partial-sum tables of the diagonal sweep (p.dslo, p.dshi)
 hipError_t launch_diag_tables(const sylt_plan_s &p, hipStream_t s);

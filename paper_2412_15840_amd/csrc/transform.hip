@@ -174,14 +174,14 @@ __device__ __forceinline__ int fibre_base(const PassDesc &pa, const TileCoord &t
 // ------------------------------------------------------------ transform
 // NN > 0: every mode of the group has extent NN.  NN == 0: mixed extents <= 24.
 template <typename V, int NN>
-__global__ void __launch_bounds__(kThreads) transform_pass_kernel(V *__restrict__ X,
+__global__ void __launch_bounds__(kThreads) transform_pass_kernel(V *X, const V *Xs,
                                                                   const V *__restrict__ Mbuf,
                                                                   PassDesc pa)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V *tile = reinterpret_cast<V *>(smem_raw);
     const TileCoord tc = tile_coord(pa);
-    load_tile<V, V>(tile, X, pa, tc);
+    load_tile<V, V>(tile, Xs, pa, tc);
     __syncthreads();
     for (int q = 0; q < pa.ng; ++q) {
         const int n = NN > 0 ? NN : pa.gd[q];
@@ -255,7 +255,7 @@ __device__ __forceinline__ TileCoord tile_coord_of(const PassDesc &pa, int64_t t
 }
 
 template <typename V, int NN, int P>
-__global__ void __launch_bounds__(kPipeThreads) transform_pipe_kernel(V *__restrict__ X,
+__global__ void __launch_bounds__(kPipeThreads) transform_pipe_kernel(V *X, const V *Xs,
                                                                       const V *__restrict__ Mbuf,
                                                                       PassDesc pa)
 {
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(kPipeThreads) transform_pipe_kernel(V *__restr
             const bool ok = lr[i] >= 0 &&
                             (whole || ((lr[i] & 0xffff) < c.lbe && (lr[i] >> 16) < c.rbe));
             if (ok) {
-                const V v = X[org + off[i]];
+                const V v = Xs[org + off[i]];
                 pre_re[i] = v.x;
                 pre_im[i] = v.y;
             }
@@ -397,7 +397,7 @@ constexpr int kMfmaThreads = 512;
 constexpr int kMfmaRegs = 16;  // tile entries per lane (tiles <= 8192 entries)
 
 template <typename V, int NN>
-__global__ void __launch_bounds__(kMfmaThreads) transform_mfma_kernel(V *__restrict__ X,
+__global__ void __launch_bounds__(kMfmaThreads) transform_mfma_kernel(V *X, const V *Xs,
                                                                       const V *__restrict__ Mbuf,
                                                                       PassDesc pa)
 {
@@ -449,7 +449,7 @@ __global__ void __launch_bounds__(kMfmaThreads) transform_mfma_kernel(V *__restr
             bool ok;
             const int64_t a = entry_addr(c, threadIdx.x + i * kMfmaThreads, ok);
             if (ok) {
-                const V v = X[a];
+                const V v = Xs[a];
                 pre_re[i] = v.x;
                 pre_im[i] = v.y;
             }
@@ -530,13 +530,13 @@ __global__ void __launch_bounds__(kMfmaThreads) transform_mfma_kernel(V *__restr
 // extents up to 64: ping-pong between two LDS tiles
 template <typename V>
 __global__ void __launch_bounds__(kThreads) transform_pass_generic_kernel(
-    V *__restrict__ X, const V *__restrict__ Mbuf, PassDesc pa)
+    V *X, const V *Xs, const V *__restrict__ Mbuf, PassDesc pa)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V *bufA = reinterpret_cast<V *>(smem_raw);
     V *bufB = bufA + (int64_t)pa.lb * pa.G * pa.rb;
     const TileCoord tc = tile_coord(pa);
-    load_tile<V, V>(bufA, X, pa, tc);
+    load_tile<V, V>(bufA, Xs, pa, tc);
     __syncthreads();
     for (int q = 0; q < pa.ng; ++q) {
         const int n = pa.gd[q];
@@ -811,7 +811,7 @@ hipError_t allow_lds(K kernel, size_t bytes)
 }
 
 template <typename V>
-hipError_t run_transform_pass(const PassDesc &pa, V *X, const V *Mbuf, hipStream_t s)
+hipError_t run_transform_pass(const PassDesc &pa, V *X, const V *Xs, const V *Mbuf, hipStream_t s)
 {
     const int64_t tiles = pa.ntl * pa.ntr;
     const bool generic = pa.maxn > 24;
@@ -821,7 +821,7 @@ hipError_t run_transform_pass(const PassDesc &pa, V *X, const V *Mbuf, hipStream
     do {                                                                                  \
         e = allow_lds(KER, lds);                                                          \
         if (e != hipSuccess) return e;                                                    \
-        hipLaunchKernelGGL(KER, dim3((unsigned)tiles), dim3(kThreads), lds, s, X, Mbuf, pa); \
+        hipLaunchKernelGGL(KER, dim3((unsigned)tiles), dim3(kThreads), lds, s, X, Xs, Mbuf, pa); \
     } while (0)
     const bool pipe = !generic && pa.lb * pa.G * pa.rb <= kPipeRegs * kPipeThreads &&
                       (pa.uniform_n == 2 || pa.uniform_n == 4 || pa.uniform_n == 8 ||
@@ -844,7 +844,7 @@ hipError_t run_transform_pass(const PassDesc &pa, V *X, const V *Mbuf, hipStream
                 hipSuccess || occ < 1)                                                         \
             occ = 1;                                                                           \
         const int64_t grid = std::min<int64_t>(tiles, (int64_t)cus * occ);                     \
-        hipLaunchKernelGGL(ker, dim3((unsigned)grid), dim3(kPipeThreads), lds, s, X, Mbuf, pa); \
+        hipLaunchKernelGGL(ker, dim3((unsigned)grid), dim3(kPipeThreads), lds, s, X, Xs, Mbuf, pa); \
     } while (0)
         static int max_lds = 0;
         if (!max_lds) {
@@ -873,7 +873,7 @@ hipError_t run_transform_pass(const PassDesc &pa, V *X, const V *Mbuf, hipStream
                 hipSuccess || occ < 1)                                                          \
             occ = 1;                                                                            \
         const int64_t grid = std::min<int64_t>(tiles, (int64_t)cus * occ);                      \
-        hipLaunchKernelGGL(ker, dim3((unsigned)grid), dim3(kMfmaThreads), ldsm, s, X, Mbuf, pa); \
+        hipLaunchKernelGGL(ker, dim3((unsigned)grid), dim3(kMfmaThreads), ldsm, s, X, Xs, Mbuf, pa); \
     } while (0)
         switch (pa.uniform_n) {
             case 2: SYLT_PIPE(2, 1); break;
@@ -908,11 +908,25 @@ hipError_t launch_transform(const sylt_plan_s &p, int dir, int precision, void *
         hipError_t e;
         if (precision == SYLT_FP64) {
             const double2 *M = dir == SYLT_TO_SCHUR ? p.dUh : p.dU;
-            e = run_transform_pass<double2>(pa, static_cast<double2 *>(X), M, s);
+            double2 *Xd = static_cast<double2 *>(X);
+            e = run_transform_pass<double2>(pa, Xd, Xd, M, s);
         } else {
             const float2 *M = dir == SYLT_TO_SCHUR ? p.dUh32 : p.dU32;
-            e = run_transform_pass<float2>(pa, static_cast<float2 *>(X), M, s);
+            float2 *Xf = static_cast<float2 *>(X);
+            e = run_transform_pass<float2>(pa, Xf, Xf, M, s);
         }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_transform_from(const sylt_plan_s &p, int dir, const double2 *src, double2 *X,
+                                 hipStream_t s)
+{
+    if (p.passes.empty()) return src == X ? hipSuccess : launch_copy_c128(X, src, p.ntot, s);
+    const double2 *M = dir == SYLT_TO_SCHUR ? p.dUh : p.dU;
+    for (size_t i = 0; i < p.passes.size(); ++i) {
+        const hipError_t e = run_transform_pass<double2>(p.passes[i], X, i == 0 ? src : X, M, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -928,7 +942,7 @@ size_t residual_mfma_lds(const PassDesc &pa)
 hipError_t launch_transform_with(const sylt_plan_s &p, const double2 *M, double2 *X, hipStream_t s)
 {
     for (const PassDesc &pa : p.passes) {
-        const hipError_t e = run_transform_pass<double2>(pa, X, M, s);
+        const hipError_t e = run_transform_pass<double2>(pa, X, X, M, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -140,6 +140,10 @@ int sylt_transform(sylt_plan p, int dir, int precision, void *X, void *stream);
  * are processed in descending hyperplanes i_1+..+i_N = s, which are mutually
  * independent (any order that computes dependencies first is valid, Section 2).
  * op = C: sum_k T_k^* x_k Y = C (ascending hyperplanes).
+ * If every T_k of the plan is diagonal to rounding (normal A_k, Remark 1), the
+ * sweep is the Hadamard product y_i = c_i / sum_k lambda_{k,i_k} (eq.
+ * e:yi1i2iNdiag), one streaming pass; sylt_plan_describe reports which form
+ * the plan uses.
  * precision = FP64: CY complex128.  MIXED: CY complex64, arithmetic in FP64.
  */
 int sylt_sweep(sylt_plan p, int op, int precision, void *CY, void *stream);

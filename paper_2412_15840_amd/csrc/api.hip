@@ -486,7 +486,6 @@ int init_plan(sylt_plan_s *p, int N, const int64_t *n)
     return plan_sweep(*p);
 }
 
-// separation into the tail of the scratch, then one synchronisation
 // Remark 1: if every T_k is diagonal to rounding (each strictly upper entry
 // at most 64 n_k eps max|T_k|, as for normal A_k), the sweep becomes the
 // Hadamard product with the inverse eigenvalue sums; build its two tables.
@@ -523,6 +522,7 @@ int plan_diagonal(sylt_plan_s *p, hipStream_t s)
     return SYLT_OK;
 }
 
+// separation into the tail of the scratch, then one synchronisation
 int finish_plan(sylt_plan_s *p, hipStream_t s, bool check_schur)
 {
     SYLT_TRY(launch_prepare_factors(*p, s));
@@ -557,7 +557,7 @@ int64_t mixed_workspace(const sylt_plan_s *p)
 
 extern "C" {
 
-int sylt_version(void) { return 100; }
+int sylt_version(void) { return 101; }
 
 const char *sylt_status_string(int code)
 {

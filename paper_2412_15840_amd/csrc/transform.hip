@@ -827,13 +827,7 @@ hipError_t run_transform_pass(const PassDesc &pa, V *X, const V *Xs, const V *Mb
                       (pa.uniform_n == 2 || pa.uniform_n == 4 || pa.uniform_n == 8 ||
                        pa.uniform_n == 16 || pa.uniform_n == 19);
     if (pipe) {
-        static int cus = 0;
-        if (!cus) {
-            int dev = 0;
-            if (hipGetDevice(&dev) != hipSuccess ||
-                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-                cus = 256;
-        }
+        const int cus = device_cus();  // of the current device (attributes are per device)
 #define SYLT_PIPE(NNV, PV)                                                                     \
     do {                                                                                       \
         auto ker = transform_pipe_kernel<V, NNV, PV>;                                          \
@@ -846,14 +840,7 @@ hipError_t run_transform_pass(const PassDesc &pa, V *X, const V *Xs, const V *Mb
         const int64_t grid = std::min<int64_t>(tiles, (int64_t)cus * occ);                     \
         hipLaunchKernelGGL(ker, dim3((unsigned)grid), dim3(kPipeThreads), lds, s, X, Xs, Mbuf, pa); \
     } while (0)
-        static int max_lds = 0;
-        if (!max_lds) {
-            int dev = 0;
-            if (hipGetDevice(&dev) != hipSuccess ||
-                hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
-                    hipSuccess)
-                max_lds = 65536;
-        }
+        const size_t max_lds = max_lds_bytes();
         // the MFMA variant also keeps the real-form matrix fragments in LDS;
         // if they do not fit next to the tile, the VALU variant runs instead
 #define SYLT_MFMA(NNV, PV)                                                                      \
@@ -861,7 +848,7 @@ hipError_t run_transform_pass(const PassDesc &pa, V *X, const V *Xs, const V *Mb
         constexpr int RBv = (2 * NNV + 15) / 16, KSv = (2 * NNV + 3) / 4;                       \
         const size_t ldsm =                                                                     \
             lds + (size_t)pa.ng * RBv * KSv * 64 * sizeof(typename CTraits<V>::R);             \
-        if (ldsm > (size_t)max_lds) {                                                           \
+        if (ldsm > max_lds) {                                                                   \
             SYLT_PIPE(NNV, PV);                                                                 \
             break;                                                                              \
         }                                                                                       \

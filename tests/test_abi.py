@@ -40,7 +40,7 @@ def test_status_strings(L):
         s = L.sylt_status_string(code)
         assert s and s != b"unknown status"
     assert L.sylt_status_string(5) == b"unknown status"
-    assert L.sylt_version() == 100
+    assert L.sylt_version() == 101
 
 
 def _dims(n):

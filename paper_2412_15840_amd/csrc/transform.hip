@@ -747,7 +747,7 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
                 typename MT::acc d[RB];
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) d[rb] = typename MT::acc{0, 0, 0, 0};
-#pragma unroll 2
+#pragma unroll
                 for (int kk = 0; kk < KS; ++kk) {
                     const int k = 4 * kk + kb;
                     const int m = k >> 1;

@@ -14,8 +14,8 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests need a device; on a CPU-only host they are skipped rather than failed
-    # (the driver selects them with -m gpu on the GPU machine).
+    # GPU tests need a device; on a CPU-only host they are skipped rather than
+    # failed (select them with -m gpu on a machine with an MI355X).
     try:
         import torch
         has_gpu = torch.cuda.is_available()

@@ -88,3 +88,29 @@ def test_hadamard_sweep_matches_the_formula(op):
     sylt.sweep(plan, Y, sylt.OP_N if op == "N" else sylt.OP_C)
     ref = c / den.ravel(order="F")
     assert relmax(host(Y), ref) <= 1e-14
+
+
+def test_mixed_precision_solve_with_normal_matrices():
+    # the FP32-storage form of the Hadamard sweep inside iterative refinement
+    sylt = _sylt()
+    rng = np.random.default_rng(10)
+    n = (8, 8, 8)
+    A = [normal_matrix(k, rng) for k in n]
+    b = crandn(int(np.prod(n)), rng)
+    plan = sylt.Plan.factor(list(n), [dev(a) for a in A])
+    assert plan.describe()["sweep"]["diagonal"] is True
+    X, info = sylt.solve(plan, dev(b), precision="mixed", info=True)
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-12
+    assert relmax(host(X), oracle.solve(n, A, b)) <= 1e-10
+
+
+def test_evolution_with_normal_matrices():
+    sylt = _sylt()
+    rng = np.random.default_rng(11)
+    n = (6, 1, 5, 4)
+    A = [normal_matrix(k, rng) for k in n]
+    b, x0 = crandn(int(np.prod(n)), rng), crandn(int(np.prod(n)), rng)
+    plan = sylt.Plan.factor(list(n), [dev(a) for a in A])
+    assert plan.describe()["sweep"]["diagonal"] is True
+    X = host(sylt.evolve(plan, 0.2, dev(b), dev(x0)))
+    assert relmax(X, oracle.evolve(n, A, b, x0, 0.2)) <= 1e-11

@@ -549,7 +549,7 @@ int check_ptrs(int N, const double *const *P)
 
 int64_t mixed_workspace(const sylt_plan_s *p)
 {
-    const int64_t r64 = p->rpasses.size() > 1 ? p->ntot * (int64_t)sizeof(double2) : 0;
+    const int64_t r64 = residual_pass_count(*p) > 1 ? p->ntot * (int64_t)sizeof(double2) : 0;
     return r64 + p->ntot * (int64_t)sizeof(float2) + 256;
 }
 
@@ -770,7 +770,7 @@ int sylt_solve(sylt_plan p, const sylt_opts *o, const double *B, double *X, void
     if (!ws || (int64_t)ws_bytes < mixed_workspace(p)) return SYLT_E_WORKSPACE;
     char *w = static_cast<char *>(ws);
     double2 *R64 = nullptr;
-    if (p->rpasses.size() > 1) {
+    if (residual_pass_count(*p) > 1) {
         R64 = reinterpret_cast<double2 *>(w);
         w += p->ntot * sizeof(double2);
     }
@@ -827,7 +827,7 @@ int sylt_evolve(sylt_plan p, double t, const double *B, const double *X0, double
     // Y(0) = U^*-chain(X0), held in X
     SYLT_TRY(launch_transform_from(*p, SYLT_TO_SCHUR, reinterpret_cast<const double2 *>(X0), Xc, s));
     // W = sum_k T_k x_k Y(0) + C, as C - sum_k (-T_k) x_k Y(0)
-    if (!p->rpasses.empty())
+    if (residual_pass_count(*p) > 0)
         SYLT_TRY(launch_residual_with(*p, p->dTneg, C, Xc, W, nullptr, nullptr, s));
     else  // every mode is a singleton: W = C + (sum a_k) Y(0)
         SYLT_TRY(launch_lincomb(W, C, Xc, p->dEvo + 2, n, s));

@@ -232,6 +232,11 @@ hipError_t launch_diag_tables(const sylt_plan_s &p, hipStream_t s);
 hipError_t launch_residual(const sylt_plan_s &p, const double2 *B, const double2 *X, double2 *R64,
                            float2 *R32, double *norms2_dev, hipStream_t s);
 // the same with the matrices M_k of Mbuf (offsets p.moff) in place of A_k
+// passes of the residual as launched (matrix-core or VALU list)
+inline size_t residual_pass_count(const sylt_plan_s &p)
+{
+    return p.residual_mfma ? p.mrpasses.size() : p.rpasses.size();
+}
 // LDS bytes of the matrix-core residual pass (two tiles and the A fragments)
 size_t residual_mfma_lds(const PassDesc &pa);
 hipError_t launch_residual_with(const sylt_plan_s &p, const double2 *Mbuf, const double2 *B,

@@ -565,6 +565,10 @@ struct SingletonList {
     int64_t off[kMaxModes];  // offsets of the 1x1 A_k in the matrix buffer
 };
 
+__device__ __forceinline__ void residual_reduce(double sb, double sr, int first, int last,
+                                                double *part_b, double *part_r, int64_t tile,
+                                                unsigned char *smem_raw);
+
 // R = src - acc on the tile (src = B in the first pass, R after), written as
 // complex128 (and complex64 in the last pass if R32); per-tile partial sums of
 // |B|^2 (first pass) and |R|^2 (last pass) in a fixed order.
@@ -596,7 +600,15 @@ __device__ __forceinline__ void residual_finish(const double2 *__restrict__ B, d
             if (!last || !R32) R[gi] = v;
         }
     }
-    // block reduction (fixed order: wave shuffles then LDS)
+    residual_reduce(sb, sr, first, last, part_b, part_r, tile, smem_raw);
+}
+
+// per-tile partial sums of |B|^2 and |R|^2: block reduction in a fixed order
+// (wave shuffles, then LDS)
+__device__ __forceinline__ void residual_reduce(double sb, double sr, int first, int last,
+                                                double *part_b, double *part_r, int64_t tile,
+                                                unsigned char *smem_raw)
+{
     __syncthreads();
     double *red = reinterpret_cast<double *>(smem_raw);
     for (int off = 32; off > 0; off >>= 1) {
@@ -702,7 +714,10 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
     const int64_t ntiles = pa.ntl * pa.ntr;
     int64_t t = blockIdx.x;
     if (t >= ntiles) return;
-    double pre_re[kResidualRegs], pre_im[kResidualRegs];
+    // X and the combine source (B in the first pass, R after) of the next
+    // tile are both prefetched into registers
+    const double2 *src = first ? B : R;
+    double pre_re[kResidualRegs], pre_im[kResidualRegs], src_re[kResidualRegs], src_im[kResidualRegs];
     auto load_regs = [&](const TileCoord &c) {
 #pragma unroll
         for (int i = 0; i < kResidualRegs; ++i) {
@@ -711,18 +726,24 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
             const int rest = e >> pa.lbshift;
             const int g = rest % (int)pa.G, r = rest / (int)pa.G;
             if (e < total && l < c.lbe && r < c.rbe) {
-                const double2 v = X[c.l0 + l + pa.Lin * (g + pa.G * (c.r0 + r))];
+                const int64_t gi = c.l0 + l + pa.Lin * (g + pa.G * (c.r0 + r));
+                const double2 v = X[gi], w = src[gi];
                 pre_re[i] = v.x;
                 pre_im[i] = v.y;
+                src_re[i] = w.x;
+                src_im[i] = w.y;
             }
         }
     };
     TileCoord tc = tile_coord_of(pa, t);
     load_regs(tc);
     while (true) {
+        double cur_re[kResidualRegs], cur_im[kResidualRegs];
 #pragma unroll
         for (int i = 0; i < kResidualRegs; ++i) {
             const int e = threadIdx.x + i * kMfmaThreads;
+            cur_re[i] = src_re[i];
+            cur_im[i] = src_im[i];
             if (e < total) {
                 const double2 x = make_double2(pre_re[i], pre_im[i]);
                 xt[e] = x;
@@ -769,7 +790,29 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
             }
             __syncthreads();
         }
-        residual_finish(B, R, R32, acc, pa, tc, first, last, part_b, part_r, t, smem_raw);
+        // R = src - acc, with this tile's source values kept in registers
+        // (cur_*) while the next tile's were prefetched
+        double sb = 0.0, sr = 0.0;
+#pragma unroll
+        for (int i = 0; i < kResidualRegs; ++i) {
+            const int e = threadIdx.x + i * kMfmaThreads;
+            const int l = e & (pa.lb - 1);
+            const int rest = e >> pa.lbshift;
+            const int g = rest % (int)pa.G, r = rest / (int)pa.G;
+            if (e < total && l < tc.lbe && r < tc.rbe) {
+                const int64_t gi = tc.l0 + l + pa.Lin * (g + pa.G * (tc.r0 + r));
+                const double2 sv = make_double2(cur_re[i], cur_im[i]);
+                const double2 a = acc[e];
+                const double2 v = make_double2(sv.x - a.x, sv.y - a.y);
+                if (first) sb += sv.x * sv.x + sv.y * sv.y;
+                if (last) {
+                    sr += v.x * v.x + v.y * v.y;
+                    if (R32) R32[gi] = make_float2((float)v.x, (float)v.y);
+                }
+                if (!last || !R32) R[gi] = v;
+            }
+        }
+        residual_reduce(sb, sr, first, last, part_b, part_r, t, smem_raw);
         if (tn >= ntiles) break;
         __syncthreads();
         t = tn;

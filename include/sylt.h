@@ -28,6 +28,10 @@
  *  - Limits: 1 <= N <= 32, 1 <= n_k <= 64, prod n_k < 2^62.
  *  - Return value: a sylt_status code (0 = success).  Argument checks run on
  *    the host before any HIP call and return synchronously.
+ *  - A plan owns small device buffers that its calls reuse (reduction
+ *    partial sums, the exp(t T_k) of the last evolution).  Calls on one plan
+ *    must therefore not run concurrently: issue them on one stream, or order
+ *    them.  Distinct plans are independent.
  */
 #ifndef SYLT_H
 #define SYLT_H

@@ -25,7 +25,7 @@
  *    Work is enqueued on it without host synchronisation unless stated.
  *  - Singleton modes (n_k = 1) may appear at any position: A_k is then a
  *    scalar that joins the eigenvalue sums (Section 4, singleton handling).
- *  - Limits: 1 <= N <= 32, 1 <= n_k <= 64, prod n_k < 2^62.
+ *  - Limits: 1 <= N <= 32, 1 <= n_k <= 256, prod n_k < 2^62.
  *  - Return value: a sylt_status code (0 = success).  Argument checks run on
  *    the host before any HIP call and return synchronously.
  *  - A plan owns small device buffers that its calls reuse (reduction
@@ -50,7 +50,7 @@ typedef enum {
     SYLT_E_NO_CONVERGENCE = -3, /* Schur QR iteration or iterative refinement did not converge */
     SYLT_E_OUT_OF_MEMORY = -4,  /* plan allocation failed */
     SYLT_E_DEVICE = -5,         /* a HIP runtime call failed */
-    SYLT_E_UNSUPPORTED = -6,    /* valid problem outside this build's limits (n_k > 64, N > 32) */
+    SYLT_E_UNSUPPORTED = -6,    /* valid problem outside the limits (n_k > 256, N > 32) */
     SYLT_E_WORKSPACE = -7       /* workspace pointer null or smaller than sylt_workspace_bytes() */
 } sylt_status;
 

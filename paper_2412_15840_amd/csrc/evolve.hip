@@ -3,7 +3,7 @@
 // triangular Schur factors (eq. e:exptAj), the scalars contributed by the
 // singleton modes, and an elementwise linear combination.
 //
-// exp(t T) for an upper triangular T (n <= 64) by scaling and squaring of a
+// exp(t T) for an upper triangular T (n <= 256) by scaling and squaring of a
 // truncated Taylor series: with s the smallest integer such that
 // ||t T||_1 / 2^s <= 1/2, exp(X) for X = t T / 2^s is summed to degree 18 by
 // Horner's rule, P <- I + X P / k for k = 18, ..., 1 (the remainder is below
@@ -36,7 +36,7 @@ __device__ void triu_product(double2 *C, const double2 *A, const double2 *B, int
     }
 }
 
-// the three work matrices of a mode live in global memory (n up to 64); the
+// the three work matrices of a mode live in global memory (n up to 256); the
 // block barrier orders their writes and reads within the workgroup
 __global__ void __launch_bounds__(kExpThreads) expm_triu_kernel(ExpJobs jobs,
                                                                 const double2 *__restrict__ T,

@@ -120,9 +120,10 @@ unsigned grid_for(int64_t n)
 
 // ------------------------------------------------------------ grad A
 // grad_{A_k}(a, m) = -sum over fibres (l, r) of G[l, a, r] conj(X[l, m, r])
-// with the tensor viewed as (L, n, R).  Stage 1: each workgroup stages FB
-// fibres of G and X in LDS and writes its n x n partial sum; stage 2 adds the
-// partials in a fixed order (deterministic) and negates.
+// with the tensor viewed as (L, n, R).  Stage 1: the fibres are cut into
+// chunks of FB; a workgroup stages one chunk of G and X at a time in LDS and
+// adds its n x n contribution into its own partial sum (chunks b, b + grid,
+// ...); stage 2 adds the partials in a fixed order (deterministic) and negates.
 __global__ void __launch_bounds__(kThreads) grad_partial_kernel(const double2 *__restrict__ G,
                                                                 const double2 *__restrict__ X,
                                                                 int64_t L, int n, int64_t R,
@@ -132,28 +133,34 @@ __global__ void __launch_bounds__(kThreads) grad_partial_kernel(const double2 *_
     double2 *gt = reinterpret_cast<double2 *>(smem_raw);
     double2 *xt = gt + (int64_t)FB * n;
     const int64_t nfib = L * R;
-    const int64_t f0 = (int64_t)blockIdx.x * FB;
-    const int nf = (int)std::min<int64_t>(FB, nfib - f0);
-    for (int e = threadIdx.x; e < nf * n; e += blockDim.x) {
-        const int fl = e % nf, m = e / nf;
-        const int64_t f = f0 + fl;
-        const int64_t l = f % L, r = f / L;
-        const int64_t gi = l + L * (m + (int64_t)n * r);
-        gt[fl + nf * m] = G[gi];
-        xt[fl + nf * m] = X[gi];
-    }
-    __syncthreads();
-    for (int pair = threadIdx.x; pair < n * n; pair += blockDim.x) {
-        const int a = pair % n, m = pair / n;
-        double2 acc = make_double2(0.0, 0.0);
-        for (int fl = 0; fl < nf; ++fl) {
-            const double2 g = gt[fl + nf * a], x = xt[fl + nf * m];
-            acc.x = fma(g.x, x.x, acc.x);
-            acc.x = fma(g.y, x.y, acc.x);
-            acc.y = fma(g.y, x.x, acc.y);
-            acc.y = fma(-g.x, x.y, acc.y);
+    const int64_t nchunks = (nfib + FB - 1) / FB;
+    double2 *mine = partial + (int64_t)blockIdx.x * n * n;
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int64_t f0 = c * FB;
+        const int nf = (int)std::min<int64_t>(FB, nfib - f0);
+        for (int e = threadIdx.x; e < nf * n; e += blockDim.x) {
+            const int fl = e % nf, m = e / nf;
+            const int64_t f = f0 + fl;
+            const int64_t l = f % L, r = f / L;
+            const int64_t gi = l + L * (m + (int64_t)n * r);
+            gt[fl + nf * m] = G[gi];
+            xt[fl + nf * m] = X[gi];
         }
-        partial[(int64_t)blockIdx.x * n * n + pair] = acc;
+        __syncthreads();
+        const bool first = c == blockIdx.x;
+        for (int pair = threadIdx.x; pair < n * n; pair += blockDim.x) {
+            const int a = pair % n, m = pair / n;
+            double2 acc = first ? make_double2(0.0, 0.0) : mine[pair];
+            for (int fl = 0; fl < nf; ++fl) {
+                const double2 g = gt[fl + nf * a], x = xt[fl + nf * m];
+                acc.x = fma(g.x, x.x, acc.x);
+                acc.x = fma(g.y, x.y, acc.x);
+                acc.y = fma(g.y, x.x, acc.y);
+                acc.y = fma(-g.x, x.y, acc.y);
+            }
+            mine[pair] = acc;
+        }
+        __syncthreads();
     }
 }
 
@@ -168,6 +175,15 @@ __global__ void grad_final_kernel(const double2 *__restrict__ partial, int nbloc
 }
 
 int grad_fibres_per_block(int n) { return std::max(1, 2048 / n); }
+
+// workgroups of stage 1: one per chunk, at most kGradMaxBlocks (which bounds
+// the partial sums at kGradMaxBlocks n^2 entries)
+constexpr int64_t kGradMaxBlocks = 512;
+int64_t grad_blocks(int64_t nfib, int n)
+{
+    const int FB = grad_fibres_per_block(n);
+    return std::max<int64_t>(1, std::min<int64_t>((nfib + FB - 1) / FB, kGradMaxBlocks));
+}
 
 }  // namespace
 
@@ -219,9 +235,7 @@ size_t grad_A_workspace(const sylt_plan_s &p)
     size_t need = 0;
     for (int k = 0; k < p.N; ++k) {
         const int n = (int)p.n[k];
-        const int64_t nfib = p.ntot / n;
-        const int FB = grad_fibres_per_block(n);
-        const int64_t blocks = (nfib + FB - 1) / FB;
+        const int64_t blocks = grad_blocks(p.ntot / n, n);
         need = std::max(need, (size_t)blocks * n * n * sizeof(double2));
     }
     return need;
@@ -239,8 +253,7 @@ hipError_t launch_grad_A(const sylt_plan_s &p, const double2 *G, const double2 *
         for (int j = 0; j < k; ++j) L *= p.n[j];
         for (int j = k + 1; j < p.N; ++j) R *= p.n[j];
         const int FB = grad_fibres_per_block(n);
-        const int64_t blocks = (L * R + FB - 1) / FB;
-        if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+        const int64_t blocks = grad_blocks(L * R, n);
         const size_t lds = (size_t)2 * FB * n * sizeof(double2);
         hipLaunchKernelGGL(grad_partial_kernel, dim3((unsigned)blocks), dim3(kThreads), lds, s, G, X,
                            L, n, R, FB, partial);

@@ -1,7 +1,10 @@
 // Complex Schur factorisation A = U T U^* on the device (Section 2 of the
 // paper: every A_j is reduced to upper-triangular T_j by a unitary U_j).
 //
-// One 64-lane workgroup per matrix (n <= 64), both H and U resident in LDS:
+// One workgroup per matrix.  For n <= 64 one 64-lane wave holds H and U in
+// LDS; larger matrices (up to 256) keep H and U in a global work buffer (L2
+// resident) and use 256 lanes, the block barriers ordering their accesses
+// within the workgroup.  Steps:
 //  1. Householder reduction to upper Hessenberg form, accumulating U.
 //  2. Single-shift complex QR iteration on the active unreduced window with a
 //     Wilkinson shift (exceptional shifts every 10 iterations without
@@ -19,6 +22,7 @@ namespace {
 struct SchurJobs {
     int count;
     int n[kMaxModes];
+    int mode[kMaxModes];  // status slot of the job
     int64_t off[kMaxModes];
 };
 
@@ -43,25 +47,28 @@ __device__ inline void givens(double2 a, double2 b, double &c, double2 &s)
     s = cscale(cmul(ph, cconj(b)), 1.0 / rho);
 }
 
-__global__ void __launch_bounds__(64) schur_kernel(SchurJobs jobs, const double2 *__restrict__ A,
+template <int NT, bool GLOBAL>
+__global__ void __launch_bounds__(NT) schur_kernel(SchurJobs jobs, const double2 *__restrict__ A,
                                                    double2 *__restrict__ Uout,
                                                    double2 *__restrict__ Tout, int *status,
-                                                   int max_iter_per_n)
+                                                   int max_iter_per_n, double2 *work,
+                                                   int64_t mtotal)
 {
     extern __shared__ double2 smem[];
     const int job = blockIdx.x;
     const int n = jobs.n[job];
     const int64_t off = jobs.off[job];
     const int tid = threadIdx.x;
-    double2 *H = smem;                  // n x n, column-major: H[i + n*j]
-    double2 *Q = smem + n * n;
-    double2 *v = Q + n * n;             // Householder vector (n)
+    // H and Q are n x n, column-major: H[i + n*j]
+    double2 *H = GLOBAL ? work + off : smem;
+    double2 *Q = GLOBAL ? work + mtotal + off : smem + n * n;
+    double2 *v = GLOBAL ? smem : Q + n * n;  // Householder vector (n)
     double2 *gs = v + n;                // rotation sines (n)
     double *gc = reinterpret_cast<double *>(gs + n);  // rotation cosines (n)
 #define HH(i, j) H[(i) + n * (j)]
 #define QQ(i, j) Q[(i) + n * (j)]
 
-    for (int idx = tid; idx < n * n; idx += 64) {
+    for (int idx = tid; idx < n * n; idx += NT) {
         H[idx] = A[off + idx];
         Q[idx] = cd((idx % n) == (idx / n) ? 1.0 : 0.0, 0.0);
     }
@@ -83,10 +90,10 @@ __global__ void __launch_bounds__(64) schur_kernel(SchurJobs jobs, const double2
         const double tau = 2.0 / (v0.x * v0.x + v0.y * v0.y + sig);
         const double2 beta = cscale(ph, -alpha);
         __syncthreads();
-        for (int r = k + 1 + tid; r < n; r += 64) v[r] = (r == k + 1) ? v0 : HH(r, k);
+        for (int r = k + 1 + tid; r < n; r += NT) v[r] = (r == k + 1) ? v0 : HH(r, k);
         __syncthreads();
         // left: rows k+1.., columns k..n-1:  H <- (I - tau v v^*) H
-        for (int c = k + tid; c < n; c += 64) {
+        for (int c = k + tid; c < n; c += NT) {
             double2 w = cd(0.0, 0.0);
             for (int r = k + 1; r < n; ++r) w = cmac_conj(w, v[r], HH(r, c));
             w = cscale(w, tau);
@@ -94,7 +101,7 @@ __global__ void __launch_bounds__(64) schur_kernel(SchurJobs jobs, const double2
         }
         __syncthreads();
         // right: all rows, columns k+1..:  H <- H (I - tau v v^*),  U <- U (I - tau v v^*)
-        for (int r = tid; r < n; r += 64) {
+        for (int r = tid; r < n; r += NT) {
             double2 w = cd(0.0, 0.0);
             double2 wq = cd(0.0, 0.0);
             for (int c = k + 1; c < n; ++c) {
@@ -158,7 +165,7 @@ __global__ void __launch_bounds__(64) schur_kernel(SchurJobs jobs, const double2
             mu = (den.x == 0.0 && den.y == 0.0) ? hd : csub(hd, cdiv(bc, den));
         }
         __syncthreads();
-        for (int t = lo + tid; t <= hi; t += 64) HH(t, t) = csub(HH(t, t), mu);
+        for (int t = lo + tid; t <= hi; t += NT) HH(t, t) = csub(HH(t, t), mu);
         __syncthreads();
         // H_w - mu I = Q R : rotations from the left, applied across to column n-1
         for (int k = lo; k < hi; ++k) {
@@ -170,7 +177,7 @@ __global__ void __launch_bounds__(64) schur_kernel(SchurJobs jobs, const double2
                 gs[k] = s;
             }
             __syncthreads();
-            for (int col = k + tid; col < n; col += 64) {
+            for (int col = k + tid; col < n; col += NT) {
                 const double2 x = HH(k, col), y = HH(k + 1, col);
                 HH(k, col) = cadd(cscale(x, c), cmul(s, y));
                 HH(k + 1, col) = csub(cscale(y, c), cmul(cconj(s), x));
@@ -183,29 +190,29 @@ __global__ void __launch_bounds__(64) schur_kernel(SchurJobs jobs, const double2
         for (int k = lo; k < hi; ++k) {
             const double c = gc[k];
             const double2 s = gs[k];
-            for (int r = tid; r <= k + 1; r += 64) {
+            for (int r = tid; r <= k + 1; r += NT) {
                 const double2 x = HH(r, k), y = HH(r, k + 1);
                 HH(r, k) = cadd(cscale(x, c), cmul(cconj(s), y));
                 HH(r, k + 1) = csub(cscale(y, c), cmul(s, x));
             }
-            for (int r = tid; r < n; r += 64) {
+            for (int r = tid; r < n; r += NT) {
                 const double2 x = QQ(r, k), y = QQ(r, k + 1);
                 QQ(r, k) = cadd(cscale(x, c), cmul(cconj(s), y));
                 QQ(r, k + 1) = csub(cscale(y, c), cmul(s, x));
             }
             __syncthreads();
         }
-        for (int t = lo + tid; t <= hi; t += 64) HH(t, t) = cadd(HH(t, t), mu);
+        for (int t = lo + tid; t <= hi; t += NT) HH(t, t) = cadd(HH(t, t), mu);
         __syncthreads();
     }
 
     // ---- 3. write U and T (strictly lower part of T exactly zero)
-    for (int idx = tid; idx < n * n; idx += 64) {
+    for (int idx = tid; idx < n * n; idx += NT) {
         const int i = idx % n, j = idx / n;
         Uout[off + idx] = Q[idx];
         Tout[off + idx] = (i > j) ? cd(0.0, 0.0) : H[idx];
     }
-    if (tid == 0) status[job] = failed;
+    if (tid == 0) status[jobs.mode[job]] = failed;
 #undef HH
 #undef QQ
 }
@@ -243,21 +250,35 @@ __global__ void prepare_factors_kernel(PrepJobs jobs, const double2 *__restrict_
 
 hipError_t launch_schur(const sylt_plan_s &p, int max_iter_per_n, hipStream_t s)
 {
-    SchurJobs jobs{};
-    int nmax = 1;
+    // two launches: extents up to kSchurLdsMax in LDS, larger ones in the
+    // plan's work buffer (3 mtotal entries; H and U take two of them)
+    SchurJobs small{}, big{};
+    int nsmall = 1, nbig = 1;
     for (int k = 0; k < p.N; ++k) {  // singleton modes give U = 1, T = A
-        jobs.n[jobs.count] = (int)p.n[k];
-        jobs.off[jobs.count] = p.moff[k];
-        ++jobs.count;
-        nmax = std::max(nmax, (int)p.n[k]);
+        const int n = (int)p.n[k];
+        const bool lds = n <= kSchurLdsMax;
+        SchurJobs &j = lds ? small : big;
+        j.n[j.count] = n;
+        j.mode[j.count] = k;
+        j.off[j.count] = p.moff[k];
+        ++j.count;
+        int &nmax = lds ? nsmall : nbig;
+        nmax = std::max(nmax, n);
     }
-    if (jobs.count == 0) return hipSuccess;
-    const size_t lds = (size_t)(2 * nmax * nmax + 2 * nmax) * sizeof(double2) + nmax * sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void *)schur_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(schur_kernel, dim3(jobs.count), dim3(64), lds, s, jobs, p.dA, p.dU, p.dT,
-                       p.dStatus, max_iter_per_n);
+    if (small.count > 0) {
+        const size_t lds =
+            (size_t)(2 * nsmall * nsmall + 2 * nsmall) * sizeof(double2) + nsmall * sizeof(double);
+        hipError_t e = hipFuncSetAttribute((const void *)schur_kernel<64, false>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((schur_kernel<64, false>), dim3(small.count), dim3(64), lds, s, small,
+                           p.dA, p.dU, p.dT, p.dStatus, max_iter_per_n, p.dEw, p.mtotal);
+    }
+    if (big.count > 0) {
+        const size_t lds = (size_t)(2 * nbig) * sizeof(double2) + nbig * sizeof(double);
+        hipLaunchKernelGGL((schur_kernel<256, true>), dim3(big.count), dim3(256), lds, s, big, p.dA,
+                           p.dU, p.dT, p.dStatus, max_iter_per_n, p.dEw, p.mtotal);
+    }
     return hipGetLastError();
 }
 

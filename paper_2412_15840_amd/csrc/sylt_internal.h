@@ -13,7 +13,8 @@
 namespace sylt {
 
 constexpr int kMaxModes = 32;     // N limit of the ABI
-constexpr int kMaxExtent = 64;    // n_k limit of the ABI
+constexpr int kMaxExtent = 256;   // n_k limit of the ABI
+constexpr int kSchurLdsMax = 64;  // Schur factors with H and U in LDS up to this extent
 constexpr int kMaxGroup = 24;     // modes fused in one transform pass (n >= 2 each)
 constexpr int kSweepTileCap = 9728;   // sweep tile entries (with diagonal blocks <= 160 KB LDS)
 constexpr int kSweepThreads = 1024;   // lanes of a sweep workgroup

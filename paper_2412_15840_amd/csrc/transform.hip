@@ -57,29 +57,29 @@ __device__ __forceinline__ void fibre_fixed(V *src, V *acc, int base, int stride
     }
 }
 
-// any extent n <= 64: outputs in chunks of 8, written to a separate buffer
+// any extent: the outputs ic .. ic+7 of one fibre, written to a separate
+// buffer (so the chunks of a fibre are independent work items)
+constexpr int kGenericChunk = 8;
 template <typename V, bool ACC>
 __device__ __forceinline__ void fibre_generic(const V *src, V *dst, int base, int stride, int n,
-                                              const V *__restrict__ M)
+                                              const V *__restrict__ M, int ic)
 {
-    for (int ic = 0; ic < n; ic += 8) {
-        V y[8];
+    V y[kGenericChunk];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) y[i] = vzero<V>();
-        for (int m = 0; m < n; ++m) {
-            const V x = src[base + m * stride];
+    for (int i = 0; i < kGenericChunk; ++i) y[i] = vzero<V>();
+    for (int m = 0; m < n; ++m) {
+        const V x = src[base + m * stride];
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                if (ic + i < n) y[i] = cmac(y[i], M[ic + i + n * m], x);
-        }
+        for (int i = 0; i < kGenericChunk; ++i)
+            if (ic + i < n) y[i] = cmac(y[i], M[ic + i + n * m], x);
+    }
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            if (ic + i < n) {
-                if (ACC)
-                    dst[base + (ic + i) * stride] = vadd(dst[base + (ic + i) * stride], y[i]);
-                else
-                    dst[base + (ic + i) * stride] = y[i];
-            }
+    for (int i = 0; i < kGenericChunk; ++i) {
+        if (ic + i < n) {
+            if (ACC)
+                dst[base + (ic + i) * stride] = vadd(dst[base + (ic + i) * stride], y[i]);
+            else
+                dst[base + (ic + i) * stride] = y[i];
         }
     }
 }
@@ -527,7 +527,8 @@ __global__ void __launch_bounds__(kMfmaThreads) transform_mfma_kernel(V *X, cons
     }
 }
 
-// extents up to 64: ping-pong between two LDS tiles
+// extents above 24: ping-pong between two LDS tiles; the work items of a mode
+// are (fibre, chunk of 8 outputs) pairs
 template <typename V>
 __global__ void __launch_bounds__(kThreads) transform_pass_generic_kernel(
     V *X, const V *Xs, const V *__restrict__ Mbuf, PassDesc pa)
@@ -543,10 +544,12 @@ __global__ void __launch_bounds__(kThreads) transform_pass_generic_kernel(
         const int nfib = pa.lb * (int)(pa.G / n) * tc.rbe;
         const int stride = pa.lb * pa.gs[q];
         const V *M = Mbuf + pa.moff[q];
-        for (int f = threadIdx.x; f < nfib; f += blockDim.x) {
+        const int nchunk = (n + kGenericChunk - 1) / kGenericChunk;
+        for (int w = threadIdx.x; w < nfib * nchunk; w += blockDim.x) {
+            const int f = w % nfib;
             const int base = fibre_base(pa, tc, q, n, f);
             if (base < 0) continue;
-            fibre_generic<V, false>(bufA, bufB, base, stride, n, M);
+            fibre_generic<V, false>(bufA, bufB, base, stride, n, M, (w / nfib) * kGenericChunk);
         }
         __syncthreads();
         V *t = bufA;
@@ -655,7 +658,10 @@ __global__ void __launch_bounds__(kThreads) residual_pass_kernel(
         const int nfib = pa.lb * (int)(pa.G / n) * tc.rbe;
         const int stride = pa.lb * pa.gs[q];
         const double2 *M = Abuf + pa.moff[q];
-        for (int f = threadIdx.x; f < nfib; f += blockDim.x) {
+        // extents above 24: (fibre, chunk of 8 outputs) work items
+        const int nchunk = (NN > 0 || n <= 24) ? 1 : (n + kGenericChunk - 1) / kGenericChunk;
+        for (int w = threadIdx.x; w < nfib * nchunk; w += blockDim.x) {
+            const int f = w % nfib;
             const int base = fibre_base(pa, tc, q, n, f);
             if (base < 0) continue;
             if constexpr (NN > 0)
@@ -663,7 +669,7 @@ __global__ void __launch_bounds__(kThreads) residual_pass_kernel(
             else if (n <= 24)
                 fibre_switch<double2, true>(xt, acc, base, stride, n, M);
             else
-                fibre_generic<double2, true>(xt, acc, base, stride, n, M);
+                fibre_generic<double2, true>(xt, acc, base, stride, n, M, (w / nfib) * kGenericChunk);
         }
         __syncthreads();
     }

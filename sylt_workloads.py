@@ -57,7 +57,8 @@ class Workload:
         return int(np.prod(self.n, dtype=np.int64))
 
 
-# The five workloads of the benchmark description (shapes and seeds).
+# The workloads: the five of the benchmark description and the mixed-extent
+# shape of Section 5.1 (shapes and seeds).
 WORKLOADS = {
     "C1": Workload("C1", (8, 8, 8), 1, "fp64", "FP64, N=3, n_k=8 (512 entries)"),
     "C2": Workload("C2", (24, 16, 1, 20, 12, 8), 2, "fp64",
@@ -66,6 +67,9 @@ WORKLOADS = {
     "C3b": Workload("C3b", (19,) * 7, 32, "fp64", "FP64, N=7, n_k=19 (893,871,739 entries)"),
     "C4": Workload("C4", (19,) * 7, 32, "mixed", "mixed precision, N=7, n_k=19"),
     "C5": Workload("C5", (16,) * 5, 5, "fp64", "differentiation, N=5, n_k=16"),
+    "E1": Workload("E1", (2, 9, 33, 74, 231), 51, "fp64",
+                   "FP64, N=5, n=(2,9,33,74,231) (10,153,836 entries), the mixed-extent "
+                   "shape of Section 5.1"),
 }
 
 

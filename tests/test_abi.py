@@ -51,7 +51,7 @@ def _dims(n):
     (0, [], -1),               # no modes
     (33, [2] * 33, -6),        # more modes than supported
     (2, [3, 0], -1),           # empty extent
-    (2, [65, 2], -6),          # extent above 64
+    (2, [257, 2], -6),         # extent above 256
     (2, [-1, 2], -1),
     (31, [64] * 31, -6),       # prod n_k overflows 2^62
 ])

@@ -42,7 +42,11 @@ SHAPES = [
     (16, 16, 16),                 # n = 16 (matrix-core transform, no padding)
     (19, 19, 19, 19),             # two fused passes, the second with ragged tiles
     (33, 5),                      # extent > 24: generic transform path
-    (64, 3),                      # the largest supported extent
+    (64, 3),                      # the largest extent with the LDS Schur kernel
+    (65, 3),                      # the smallest with the global-memory Schur kernel
+    (100, 2, 3),                  # extent > 64 in the first mode
+    (3, 5, 256),                  # the largest supported extent, in the last mode
+    (2, 9, 33, 74),               # leading modes of the large-extent shape of Section 5.1
     (11,),                        # N = 1: a plain triangular solve
     (3, 1, 1, 4),
 ]

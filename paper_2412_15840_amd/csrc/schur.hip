@@ -26,7 +26,7 @@ struct SchurJobs {
     int64_t off[kMaxModes];
 };
 
-__device__ inline void givens(double2 a, double2 b, double &c, double2 &s)
+__device__ __forceinline__ void givens(double2 a, double2 b, double &c, double2 &s)
 {
     // [c s; -conj(s) c] [a; b] = [r; 0] with real c and c^2 + |s|^2 = 1
     if (b.x == 0.0 && b.y == 0.0) {
@@ -34,17 +34,173 @@ __device__ inline void givens(double2 a, double2 b, double &c, double2 &s)
         s = cd(0.0, 0.0);
         return;
     }
-    const double absb = cabs2(b);
     if (a.x == 0.0 && a.y == 0.0) {
+        const double absb = cabs2(b);
         c = 0.0;
         s = cd(b.x / absb, -b.y / absb);
         return;
     }
-    const double absa = cabs2(a);
+    // moduli in [2^-480, 2^480]: the squares are normal and finite, so
+    // c = |a| / rho and s = a conj(b) / (|a| rho) come from the sums of squares
+    // (a short dependence chain: this sits on the critical path of a QR sweep)
+    const double aa = a.x * a.x + a.y * a.y, bb = b.x * b.x + b.y * b.y;
+    if (aa > 0x1p-960 && aa < 0x1p960 && bb > 0x1p-960 && bb < 0x1p960) {
+        const double ra = sqrt(aa);
+        const double ir = 1.0 / sqrt(aa + bb);
+        c = ra * ir;
+        s = cscale(cmul(a, cconj(b)), ir / ra);
+        return;
+    }
+    const double absa = cabs2(a), absb = cabs2(b);
     const double rho = hypot(absa, absb);
     c = absa / rho;
     const double2 ph = cd(a.x / absa, a.y / absa);
     s = cscale(cmul(ph, cconj(b)), 1.0 / rho);
+}
+
+// ---- shifted QR of an upper Hessenberg H (global memory) by a 256-lane
+// workgroup, for the large-extent form.  The same rotations as the LDS version
+// below, ordered so that steps do not wait on memory round trips:
+//  * deflation: every lane tests one subdiagonal entry; an LDS maximum gives
+//    the largest negligible one (the bottom of the active window);
+//  * left rotations (H_w - mu I = Q R): lane c owns column c and carries its
+//    entry of the running row k+1; the two entries that define rotation k pass
+//    through LDS (two alternating slots, one barrier a step), every lane
+//    computes the rotation and lane 0 records it in LDS;
+//  * right rotations (R Q, then U <- U Q): lane r owns row r and carries its
+//    entry of the running column k+1; no barrier.
+// Rows (columns) are loaded in groups of kQrGroup, one group ahead: with
+// stores in flight, a wait on a load waits for every memory operation before
+// it, so the groups leave one wait per kQrGroup steps.  Loads are unconditional
+// from clamped addresses and masked afterwards (a load under a lane branch is
+// waited for at the join).
+constexpr int kQrGroup = 8;
+
+__device__ __forceinline__ int qr_block(double2 *H, double2 *Q, int n, int tid, int maxit,
+                                        double2 *gs, double *gc, double2 *bc, int *red)
+{
+    constexpr int G = kQrGroup;
+    const double eps = 2.220446049250313e-16;
+#define HH(i, j) H[(i) + n * (j)]
+    int hi = n - 1, iter = 0, total = 0;
+    while (hi > 0) {
+        if (tid == 0) *red = 0;
+        __syncthreads();
+        if (tid >= 1 && tid <= hi) {
+            double tst = cabs1(HH(tid - 1, tid - 1)) + cabs1(HH(tid, tid));
+            if (tst == 0.0) tst = 1.0;
+            if (cabs1(HH(tid, tid - 1)) <= eps * tst) atomicMax(red, tid);
+        }
+        __syncthreads();
+        const int lo = *red;
+        if (lo > 0 && tid == 0) HH(lo, lo - 1) = cd(0.0, 0.0);
+        if (lo == hi) {
+            __syncthreads();
+            --hi;
+            iter = 0;
+            continue;
+        }
+        if (++total > maxit) return 1;
+        ++iter;
+        double2 mu;
+        const double2 hd = HH(hi, hi);
+        if (iter % 10 == 0) {
+            mu = cadd(hd, cd(0.75 * cabs1(HH(hi, hi - 1)), 0.0));
+        } else {
+            const double2 a = HH(hi - 1, hi - 1), b = HH(hi - 1, hi), c = HH(hi, hi - 1);
+            const double2 p = cscale(csub(a, hd), 0.5);
+            const double2 bc2 = cmul(b, c);
+            const double2 disc = csqrt_(cadd(cmul(p, p), bc2));
+            const double2 s1 = cadd(p, disc), s2 = csub(p, disc);
+            const double2 den = cabs2(s1) >= cabs2(s2) ? s1 : s2;
+            mu = (den.x == 0.0 && den.y == 0.0) ? hd : csub(hd, cdiv(bc2, den));
+        }
+        // left rotations: this lane's entry of row r of H_w - mu I
+        const int col = tid;
+        auto ld_row = [&](int r) __attribute__((always_inline)) {
+            double2 v = HH(min(r, n - 1), min(col, n - 1));
+            if (col == r) v = csub(v, mu);
+            return (col < n && r <= hi) ? v : cd(0.0, 0.0);
+        };
+        double2 cur = ld_row(lo), ra[G], rb[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) ra[i] = ld_row(lo + 1 + i);
+        auto lstep = [&](int k, double2 R) __attribute__((always_inline)) {
+            if (k >= hi) return;
+            double2 *slot = bc + 2 * (k & 1);
+            if (col == k) {
+                slot[0] = cur;
+                slot[1] = R;
+            }
+            __syncthreads();
+            double c;
+            double2 s;
+            givens(slot[0], slot[1], c, s);
+            if (tid == 0) {
+                gc[k] = c;
+                gs[k] = s;
+            }
+            if (col >= k && col < n) {
+                HH(k, col) = cadd(cscale(cur, c), cmul(s, R));
+                cur = csub(cscale(R, c), cmul(cconj(s), cur));
+                if (col == k) HH(k + 1, k) = cd(0.0, 0.0);
+            }
+        };
+        for (int k = lo; k < hi; k += 2 * G) {
+#pragma unroll
+            for (int i = 0; i < G; ++i) rb[i] = ld_row(k + 1 + G + i);
+#pragma unroll
+            for (int i = 0; i < G; ++i) lstep(k + i, ra[i]);
+            if (k + G >= hi) break;
+#pragma unroll
+            for (int i = 0; i < G; ++i) ra[i] = ld_row(k + 1 + 2 * G + i);
+#pragma unroll
+            for (int i = 0; i < G; ++i) lstep(k + G + i, rb[i]);
+        }
+        if (col >= hi && col < n) HH(hi, col) = cur;
+        __syncthreads();
+        // right rotations on rows 0..k+1 of H (the shift returns to each
+        // diagonal entry when its column is final), then on every row of U
+        const int r = tid;
+        auto right = [&](double2 *M, bool isH) __attribute__((always_inline)) {
+            auto ld_col = [&](int j) __attribute__((always_inline)) {
+                const double2 v = M[min(r, n - 1) + n * min(j, n - 1)];
+                return (j <= hi && r < n && (!isH || r <= j)) ? v : cd(0.0, 0.0);
+            };
+            const double2 c0 = M[min(r, n - 1) + n * lo];
+            double2 cc = (r < n && (!isH || r <= lo + 1)) ? c0 : cd(0.0, 0.0);
+            double2 ya[G], yb[G];
+#pragma unroll
+            for (int i = 0; i < G; ++i) ya[i] = ld_col(lo + 1 + i);
+            auto rstep = [&](int k, double2 Y) __attribute__((always_inline)) {
+                if (k >= hi) return;
+                const double c = gc[k];
+                const double2 s = gs[k];
+                if (r < n && (!isH || r <= k + 1)) {
+                    const double2 nk = cadd(cscale(cc, c), cmul(cconj(s), Y));
+                    M[r + n * k] = (isH && r == k) ? cadd(nk, mu) : nk;
+                    cc = csub(cscale(Y, c), cmul(s, cc));
+                }
+            };
+            for (int k = lo; k < hi; k += 2 * G) {
+#pragma unroll
+                for (int i = 0; i < G; ++i) yb[i] = ld_col(k + 1 + G + i);
+#pragma unroll
+                for (int i = 0; i < G; ++i) rstep(k + i, ya[i]);
+                if (k + G >= hi) break;
+#pragma unroll
+                for (int i = 0; i < G; ++i) ya[i] = ld_col(k + 1 + 2 * G + i);
+#pragma unroll
+                for (int i = 0; i < G; ++i) rstep(k + G + i, yb[i]);
+            }
+            if (r < n && (!isH || r <= hi)) M[r + n * hi] = (isH && r == hi) ? cadd(cc, mu) : cc;
+        };
+        right(H, true);
+        right(Q, false);
+        __syncthreads();
+    }
+    return 0;
+#undef HH
 }
 
 template <int NT, bool GLOBAL>
@@ -127,6 +283,14 @@ __global__ void __launch_bounds__(NT) schur_kernel(SchurJobs jobs, const double2
     const double eps = 2.220446049250313e-16;
     int hi = n - 1, iter = 0, total = 0, failed = 0;
     const int maxit = max_iter_per_n * n;
+    if (GLOBAL) {
+        // two pairs of broadcast slots after the cosines (16-byte aligned),
+        // then the deflation maximum
+        double2 *bc = reinterpret_cast<double2 *>(gc + n + (n & 1));
+        failed = qr_block(H, Q, n, tid, maxit, gs, gc, bc, reinterpret_cast<int *>(bc + 4));
+        __syncthreads();
+        hi = 0;
+    }
     while (hi > 0) {
         // deflation scan (every lane computes the same, reading the same LDS)
         int lo = hi;
@@ -275,7 +439,9 @@ hipError_t launch_schur(const sylt_plan_s &p, int max_iter_per_n, hipStream_t s)
                            p.dA, p.dU, p.dT, p.dStatus, max_iter_per_n, p.dEw, p.mtotal);
     }
     if (big.count > 0) {
-        const size_t lds = (size_t)(2 * nbig) * sizeof(double2) + nbig * sizeof(double);
+        // v, the rotation sines and cosines, four broadcast slots (aligned)
+        // and the deflation maximum
+        const size_t lds = (size_t)(2 * nbig + 7) * sizeof(double2) + nbig * sizeof(double);
         hipLaunchKernelGGL((schur_kernel<256, true>), dim3(big.count), dim3(256), lds, s, big, p.dA,
                            p.dU, p.dT, p.dStatus, max_iter_per_n, p.dEw, p.mtotal);
     }

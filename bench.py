@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-evolve", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--phase-reps", type=int, default=3)
     return ap.parse_args()
 
@@ -340,6 +341,40 @@ def main():
                   "paper_matlab_s": 25.73, "paper_max_error": 9.6811e-14}
         log(f"advection-diffusion {advdif}")
 
+    # ---------------------------------------------------------- Section 5.1
+    # the mixed-extent shape n = (2, 9, 33, 74, 231) (10,153,836 entries):
+    # plan (device Schur, global-memory kernel for 74 and 231) + FP64 solve,
+    # with the usual synthetic coefficients and right-hand side
+    large = None
+    if not args.no_large and args.workload != "E1":
+        wE = wl.WORKLOADS["E1"]
+        AE = [torch.from_numpy(a).cuda() for a in wl.coefficient_matrices(wE.n, wE.seed)]
+        BE = torch.from_numpy(wl.rhs(wE)).cuda()
+        XE = torch.empty_like(BE)
+
+        def large_run():
+            pE = sylt.Plan.factor(list(wE.n), AE)
+            sylt.solve(pE, BE, out=XE)
+            return pE
+
+        large_run().destroy()
+        torch.cuda.synchronize()
+        t_l = time_events(lambda: large_run().destroy(), 3, torch)
+        pE = sylt.Plan.factor(list(wE.n), AE)
+        YE = BE.clone()
+        t_lp = time_events(lambda: sylt.Plan.factor(list(wE.n), AE).destroy(), 2, torch)
+        t_lf = time_events(lambda: sylt.transform(pE, YE, sylt.TO_SCHUR), reps, torch)
+        t_ls = time_events(lambda: sylt.sweep(pE, YE, sylt.OP_N), reps, torch)
+        pE.destroy()
+        trE = 8.0 * wE.ntot * sum(wE.n)
+        large = {"n": list(wE.n), "ntot": wE.ntot, "ms_per_step": round(t_l, 3),
+                 "entries_per_s": wE.ntot / (t_l * 1e-3), "plan_ms": round(t_lp, 3),
+                 "transform_ms": round(t_lf, 3), "sweep_ms": round(t_ls, 3),
+                 "transform_tflops": round(trE / (t_lf * 1e-3) / 1e12, 3),
+                 "paper_matlab_s": 27.64}
+        log(f"large extent {large}")
+        del AE, BE, XE, YE
+
     # ---------------------------------------------------------- CPU oracle
     cpu = None
     if not args.no_cpu:
@@ -360,7 +395,7 @@ def main():
         "cpu_baseline": cpu,
         "solve_roofline": solve_roof,
         "phases": phases, "kernels": kernels, "mixed": mixed, "evolve": evolve,
-        "normal_sweep": normal, "advection_diffusion": advdif,
+        "normal_sweep": normal, "advection_diffusion": advdif, "large_extent": large,
         "plan": {"transform_passes": [p["extents"] for p in desc["transform_passes"]],
                  "sweep_block": desc["sweep"]["block"], "sweep_tile_levels": n_lvl,
                  "sep": desc["sep"]},

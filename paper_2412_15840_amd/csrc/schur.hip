@@ -26,6 +26,19 @@ struct SchurJobs {
     int64_t off[kMaxModes];
 };
 
+// 1/sqrt(x) for a normal positive x: the hardware estimate refined by three
+// Newton steps y <- y + y (1 - x y^2) / 2 (quadratic convergence to rounding)
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double e = fma(-(x * y), y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
 __device__ __forceinline__ void givens(double2 a, double2 b, double &c, double2 &s)
 {
     // [c s; -conj(s) c] [a; b] = [r; 0] with real c and c^2 + |s|^2 = 1
@@ -41,14 +54,14 @@ __device__ __forceinline__ void givens(double2 a, double2 b, double &c, double2 
         return;
     }
     // moduli in [2^-480, 2^480]: the squares are normal and finite, so
-    // c = |a| / rho and s = a conj(b) / (|a| rho) come from the sums of squares
-    // (a short dependence chain: this sits on the critical path of a QR sweep)
+    // c = |a| / rho = |a|^2 / (|a| rho) and s = a conj(b) / (|a| rho) come from
+    // two independent reciprocal square roots of the sums of squares (a short
+    // dependence chain: this sits on the critical path of a QR sweep)
     const double aa = a.x * a.x + a.y * a.y, bb = b.x * b.x + b.y * b.y;
     if (aa > 0x1p-960 && aa < 0x1p960 && bb > 0x1p-960 && bb < 0x1p960) {
-        const double ra = sqrt(aa);
-        const double ir = 1.0 / sqrt(aa + bb);
-        c = ra * ir;
-        s = cscale(cmul(a, cconj(b)), ir / ra);
+        const double w = rsqrt_nr(aa) * rsqrt_nr(aa + bb);
+        c = aa * w;
+        s = cscale(cmul(a, cconj(b)), w);
         return;
     }
     const double absa = cabs2(a), absb = cabs2(b);
@@ -172,10 +185,20 @@ __device__ __forceinline__ int qr_block(double2 *H, double2 *Q, int n, int tid, 
             double2 ya[G], yb[G];
 #pragma unroll
             for (int i = 0; i < G; ++i) ya[i] = ld_col(lo + 1 + i);
-            auto rstep = [&](int k, double2 Y) __attribute__((always_inline)) {
+            // the rotations of a group come from LDS in one batch (clamped
+            // indices, no branch), so a step waits on no load
+            double cg[G];
+            double2 sg[G];
+            auto ld_rot = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+                for (int i = 0; i < G; ++i) {
+                    const int k = min(k0 + i, n - 1);
+                    cg[i] = gc[k];
+                    sg[i] = gs[k];
+                }
+            };
+            auto rstep = [&](int k, double2 Y, double c, double2 s) __attribute__((always_inline)) {
                 if (k >= hi) return;
-                const double c = gc[k];
-                const double2 s = gs[k];
                 if (r < n && (!isH || r <= k + 1)) {
                     const double2 nk = cadd(cscale(cc, c), cmul(cconj(s), Y));
                     M[r + n * k] = (isH && r == k) ? cadd(nk, mu) : nk;
@@ -185,13 +208,15 @@ __device__ __forceinline__ int qr_block(double2 *H, double2 *Q, int n, int tid, 
             for (int k = lo; k < hi; k += 2 * G) {
 #pragma unroll
                 for (int i = 0; i < G; ++i) yb[i] = ld_col(k + 1 + G + i);
+                ld_rot(k);
 #pragma unroll
-                for (int i = 0; i < G; ++i) rstep(k + i, ya[i]);
+                for (int i = 0; i < G; ++i) rstep(k + i, ya[i], cg[i], sg[i]);
                 if (k + G >= hi) break;
 #pragma unroll
                 for (int i = 0; i < G; ++i) ya[i] = ld_col(k + 1 + 2 * G + i);
+                ld_rot(k + G);
 #pragma unroll
-                for (int i = 0; i < G; ++i) rstep(k + G + i, yb[i]);
+                for (int i = 0; i < G; ++i) rstep(k + G + i, yb[i], cg[i], sg[i]);
             }
             if (r < n && (!isH || r <= hi)) M[r + n * hi] = (isH && r == hi) ? cadd(cc, mu) : cc;
         };

@@ -258,9 +258,26 @@ __global__ void __launch_bounds__(NT) schur_kernel(SchurJobs jobs, const double2
     // ---- 1. Hessenberg reduction
     for (int k = 0; k + 2 < n; ++k) {
         double sig = 0.0;
-        for (int r = k + 2; r < n; ++r) {
-            const double2 h = HH(r, k);
-            sig += h.x * h.x + h.y * h.y;
+        if constexpr (GLOBAL) {
+            // one entry per lane, summed over the wave and then over the waves
+            // in a fixed order (partials in the sine array, alternating halves
+            // by the parity of k so that the next column cannot overwrite them)
+            double part = 0.0;
+            for (int r = k + 2 + tid; r < n; r += NT) {
+                const double2 h = HH(r, k);
+                part += h.x * h.x + h.y * h.y;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+            double *red = reinterpret_cast<double *>(gs) + (k & 1) * (NT / 64);
+            if ((tid & 63) == 0) red[tid >> 6] = part;
+            __syncthreads();
+            for (int w = 0; w < NT / 64; ++w) sig += red[w];
+        } else {
+            for (int r = k + 2; r < n; ++r) {
+                const double2 h = HH(r, k);
+                sig += h.x * h.x + h.y * h.y;
+            }
         }
         if (sig == 0.0) continue;  // uniform: every lane read the same values
         const double2 x0 = HH(k + 1, k);
@@ -276,8 +293,10 @@ __global__ void __launch_bounds__(NT) schur_kernel(SchurJobs jobs, const double2
         // left: rows k+1.., columns k..n-1:  H <- (I - tau v v^*) H
         for (int c = k + tid; c < n; c += NT) {
             double2 w = cd(0.0, 0.0);
+#pragma unroll 8
             for (int r = k + 1; r < n; ++r) w = cmac_conj(w, v[r], HH(r, c));
             w = cscale(w, tau);
+#pragma unroll 8
             for (int r = k + 1; r < n; ++r) HH(r, c) = csub(HH(r, c), cmul(v[r], w));
         }
         __syncthreads();
@@ -285,12 +304,14 @@ __global__ void __launch_bounds__(NT) schur_kernel(SchurJobs jobs, const double2
         for (int r = tid; r < n; r += NT) {
             double2 w = cd(0.0, 0.0);
             double2 wq = cd(0.0, 0.0);
+#pragma unroll 8
             for (int c = k + 1; c < n; ++c) {
                 w = cmac(w, HH(r, c), v[c]);
                 wq = cmac(wq, QQ(r, c), v[c]);
             }
             w = cscale(w, tau);
             wq = cscale(wq, tau);
+#pragma unroll 8
             for (int c = k + 1; c < n; ++c) {
                 HH(r, c) = csub(HH(r, c), cmul(w, cconj(v[c])));
                 QQ(r, c) = csub(QQ(r, c), cmul(wq, cconj(v[c])));

@@ -8,7 +8,8 @@ stand in for the paper's matrices).
     about 8e-11 for its matrices; these are better conditioned, gate 1e-12
     relative to max|X|);
   * the mixed-precision form reaches a 1e-12 relative residual;
-  * the device Schur factor of the 231 x 231 matrix (global-memory kernel).
+  * the device Schur factor of the 231 x 231 matrix (global-memory kernel);
+  * the adjoint, the A-gradient and the time evolution at extents above 64.
 """
 import numpy as np
 import pytest
@@ -119,3 +120,23 @@ def test_large_extent_adjoint_and_gradient():
     assert relmax(host(GB), GBo) <= TOL
     for k in range(len(n)):
         assert relmax(host(GA[k]), oracle.grad_A(n, k, GBo, Xo)) <= TOL, k
+
+
+@pytest.mark.parametrize("n", [(70, 3), (2, 231)], ids=lambda n: "x".join(map(str, n)))
+def test_large_extent_evolve(n):
+    """Theorem 1 (sylt_evolve) with an extent above 64: the device exp(t T_k)
+    on a 70 x 70 and a 231 x 231 triangular factor against the oracle (SciPy
+    expm); gate 1e-11 as for the other evolution tests."""
+    sylt = _sylt()
+    banner(f"large evolve {n}")
+    A = wl.coefficient_matrices(n, 78)
+    ntot = int(np.prod(n))
+    B = wl.complex_normal(ntot, 78)
+    X0 = wl.complex_normal(ntot, 78, wl.W_STREAM)
+    t = 0.1
+    plan = sylt.Plan.factor(n, [torch.from_numpy(a) for a in A])
+    X = sylt.evolve(plan, t, dev(B), dev(X0))
+    torch.cuda.synchronize()
+    err = relmax(host(X), oracle.evolve(n, A, B, X0, t))
+    print(f"[large] evolve {n}: relmax {err:.3e}", flush=True)
+    assert err <= 1e-11

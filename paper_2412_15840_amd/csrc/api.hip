@@ -177,7 +177,21 @@ double sweep_cost(const sylt_plan_s &p, const std::vector<int> &b)
 
 }  // namespace
 
-int plan_sweep(sylt_plan_s &p)
+void free_sweep_tables(SweepPlan &sp)
+{
+    if (sp.arena) (void)hipFree(sp.arena);
+    sp.arena = nullptr;
+    sp.d_desc = nullptr;
+    sp.d_tiles = nullptr;
+    sp.d_goff = nullptr;
+    sp.d_code = nullptr;
+    sp.d_llist = nullptr;
+    sp.d_lloff = nullptr;
+    sp.d_lanetab = nullptr;
+    sp.level_off.clear();
+}
+
+int plan_sweep(sylt_plan_s &p, const int *force_b)
 {
     SweepPlan &sp = p.sweep;
     SweepDesc &sd = sp.desc;
@@ -197,9 +211,20 @@ int plan_sweep(sylt_plan_s &p)
         }
         return std::pair<int64_t, size_t>(S, (size_t)(S + td + 1) * sizeof(double2));
     };
+    if (force_b) {
+        // caller-chosen blocks: each a whole mode or at most the longest
+        // partial block the pull loop holds, and the tile must fit the LDS
+        for (int j = 0; j < M; ++j) {
+            if (force_b[j] < 1 || force_b[j] > p.cdim[j]) return SYLT_E_INVALID_ARG;
+            if (force_b[j] < p.cdim[j] && force_b[j] > bmax) return SYLT_E_UNSUPPORTED;
+            b[j] = force_b[j];
+        }
+        auto tb = tile_bytes(b);
+        if (tb.first > kSweepTileCap || tb.second > lds_cap) return SYLT_E_UNSUPPORTED;
+    }
     // greedy: repeatedly take the move (a larger block on one mode) with the
     // best modelled gain that still fits the LDS budget
-    for (;;) {
+    for (; !force_b;) {
         const double cur = sweep_cost(p, b);
         double best_gain = 0.0;
         int best_j = -1, best_b = 0;
@@ -388,21 +413,37 @@ int plan_sweep(sylt_plan_s &p)
             sd.rounds = 0;
         }
     }
-    SYLT_TRY(hipMalloc(&sp.d_desc, sizeof(SweepDesc)));
-    SYLT_TRY(hipMemcpy(sp.d_desc, &sd, sizeof(SweepDesc), hipMemcpyHostToDevice));
-    SYLT_TRY(hipMalloc(&sp.d_lanetab, lanetab.size() * sizeof(int)));
-    SYLT_TRY(hipMemcpy(sp.d_lanetab, lanetab.data(), lanetab.size() * sizeof(int),
-                       hipMemcpyHostToDevice));
-    SYLT_TRY(hipMalloc(&sp.d_goff, S * sizeof(int64_t)));
-    SYLT_TRY(hipMalloc(&sp.d_code, S * sizeof(uint64_t)));
-    SYLT_TRY(hipMalloc(&sp.d_llist, S * sizeof(int)));
-    SYLT_TRY(hipMalloc(&sp.d_lloff, (nll + 1) * sizeof(int)));
-    SYLT_TRY(hipMalloc(&sp.d_tiles, std::max<int64_t>(1, ntiles) * sizeof(int)));
-    SYLT_TRY(hipMemcpy(sp.d_goff, goff.data(), S * sizeof(int64_t), hipMemcpyHostToDevice));
-    SYLT_TRY(hipMemcpy(sp.d_code, code.data(), S * sizeof(uint64_t), hipMemcpyHostToDevice));
-    SYLT_TRY(hipMemcpy(sp.d_llist, llist.data(), S * sizeof(int), hipMemcpyHostToDevice));
-    SYLT_TRY(hipMemcpy(sp.d_lloff, lloff.data(), (nll + 1) * sizeof(int), hipMemcpyHostToDevice));
-    SYLT_TRY(hipMemcpy(sp.d_tiles, tiles.data(), ntiles * sizeof(int), hipMemcpyHostToDevice));
+    // every table in one device allocation, filled by one host-to-device copy
+    std::vector<std::pair<const void *, size_t>> parts = {
+        {&sd, sizeof(SweepDesc)},
+        {goff.data(), S * sizeof(int64_t)},
+        {code.data(), S * sizeof(uint64_t)},
+        {lanetab.data(), lanetab.size() * sizeof(int)},
+        {llist.data(), S * sizeof(int)},
+        {lloff.data(), (nll + 1) * sizeof(int)},
+        {tiles.data(), std::max<int64_t>(1, ntiles) * sizeof(int)},
+    };
+    if (ntiles == 0) parts.back().first = nullptr;
+    std::vector<size_t> off(parts.size());
+    size_t total = 0;
+    for (size_t i = 0; i < parts.size(); ++i) {
+        off[i] = total;
+        total += (parts[i].second + 255) & ~size_t(255);
+    }
+    std::vector<unsigned char> staging(total, 0);
+    for (size_t i = 0; i < parts.size(); ++i)
+        if (parts[i].first) memcpy(staging.data() + off[i], parts[i].first, parts[i].second);
+    unsigned char *base = nullptr;
+    SYLT_TRY(hipMalloc(&base, total));
+    sp.arena = base;
+    sp.d_desc = reinterpret_cast<SweepDesc *>(base + off[0]);
+    sp.d_goff = reinterpret_cast<int64_t *>(base + off[1]);
+    sp.d_code = reinterpret_cast<uint64_t *>(base + off[2]);
+    sp.d_lanetab = reinterpret_cast<int *>(base + off[3]);
+    sp.d_llist = reinterpret_cast<int *>(base + off[4]);
+    sp.d_lloff = reinterpret_cast<int *>(base + off[5]);
+    sp.d_tiles = reinterpret_cast<int *>(base + off[6]);
+    SYLT_TRY(hipMemcpy(base, staging.data(), total, hipMemcpyHostToDevice));
     return SYLT_OK;
 }
 
@@ -412,32 +453,15 @@ using namespace sylt;
 
 namespace {
 
+// hipFree waits for the device work that may still use the memory, so no
+// explicit device synchronisation is needed here
 void free_plan(sylt_plan_s *p)
 {
     if (!p) return;
-    hipDeviceSynchronize();
-    hipFree(p->dA);
-    hipFree(p->dU);
-    hipFree(p->dUh);
-    hipFree(p->dT);
-    hipFree(p->dTt);
-    hipFree(p->dslo);
-    hipFree(p->dshi);
-    hipFree(p->dTneg);
-    hipFree(p->dE);
-    hipFree(p->dEw);
-    hipFree(p->dEvo);
-    hipFree(p->dU32);
-    hipFree(p->dUh32);
-    hipFree(p->dStatus);
-    hipFree(p->dScratch);
-    hipFree(p->sweep.d_tiles);
-    hipFree(p->sweep.d_goff);
-    hipFree(p->sweep.d_code);
-    hipFree(p->sweep.d_llist);
-    hipFree(p->sweep.d_lloff);
-    hipFree(p->sweep.d_lanetab);
-    hipFree(p->sweep.d_desc);
+    if (p->arena) (void)hipFree(p->arena);
+    if (p->dslo) (void)hipFree(p->dslo);
+    if (p->dshi) (void)hipFree(p->dshi);
+    free_sweep_tables(p->sweep);
     delete p;
 }
 
@@ -463,26 +487,37 @@ int init_plan(sylt_plan_s *p, int N, const int64_t *n)
         stride *= n[k];
     }
     p->M = (int)p->cmode.size();
-    const size_t mb = p->mtotal * sizeof(double2);
-    SYLT_TRY(hipMalloc(&p->dA, mb));
-    SYLT_TRY(hipMalloc(&p->dU, mb));
-    SYLT_TRY(hipMalloc(&p->dUh, mb));
-    SYLT_TRY(hipMalloc(&p->dT, mb));
-    SYLT_TRY(hipMalloc(&p->dTt, p->mtotal * sizeof(double2)));
-    SYLT_TRY(hipMalloc(&p->dTneg, p->mtotal * sizeof(double2)));
-    SYLT_TRY(hipMalloc(&p->dE, p->mtotal * sizeof(double2)));
-    SYLT_TRY(hipMalloc(&p->dEw, 3 * p->mtotal * sizeof(double2)));
-    SYLT_TRY(hipMalloc(&p->dEvo, 4 * sizeof(double2)));
-    SYLT_TRY(hipMalloc(&p->dU32, p->mtotal * sizeof(float2)));
-    SYLT_TRY(hipMalloc(&p->dUh32, p->mtotal * sizeof(float2)));
-    SYLT_TRY(hipMalloc(&p->dStatus, std::max(1, N) * sizeof(int)));
-    SYLT_TRY(hipMemset(p->dStatus, 0, std::max(1, N) * sizeof(int)));
     plan_passes(*p);
     int64_t maxt = 1;
     for (const PassDesc &pd : p->rpasses) maxt = std::max<int64_t>(maxt, pd.ntl * pd.ntr);
     for (const PassDesc &pd : p->mrpasses) maxt = std::max<int64_t>(maxt, pd.ntl * pd.ntr);
     p->scratch_bytes = (size_t)(std::max<int64_t>(2 * maxt, 4096) + 64) * sizeof(double);
-    SYLT_TRY(hipMalloc(&p->dScratch, p->scratch_bytes));
+    // the per-mode matrices, scratch and status words: one device allocation
+    const size_t m16 = p->mtotal * sizeof(double2), m8 = p->mtotal * sizeof(float2);
+    const size_t sizes[] = {m16, m16, m16, m16, m16, m16, m16, 3 * m16, 4 * sizeof(double2),
+                            m8,  m8,  p->scratch_bytes, std::max(1, N) * sizeof(int)};
+    size_t off[sizeof(sizes) / sizeof(sizes[0])], total = 0;
+    for (size_t i = 0; i < sizeof(sizes) / sizeof(sizes[0]); ++i) {
+        off[i] = total;
+        total += (sizes[i] + 255) & ~size_t(255);
+    }
+    unsigned char *base = nullptr;
+    SYLT_TRY(hipMalloc(&base, total));
+    p->arena = base;
+    p->dA = reinterpret_cast<double2 *>(base + off[0]);
+    p->dU = reinterpret_cast<double2 *>(base + off[1]);
+    p->dUh = reinterpret_cast<double2 *>(base + off[2]);
+    p->dT = reinterpret_cast<double2 *>(base + off[3]);
+    p->dTt = reinterpret_cast<double2 *>(base + off[4]);
+    p->dTneg = reinterpret_cast<double2 *>(base + off[5]);
+    p->dE = reinterpret_cast<double2 *>(base + off[6]);
+    p->dEw = reinterpret_cast<double2 *>(base + off[7]);
+    p->dEvo = reinterpret_cast<double2 *>(base + off[8]);
+    p->dU32 = reinterpret_cast<float2 *>(base + off[9]);
+    p->dUh32 = reinterpret_cast<float2 *>(base + off[10]);
+    p->dScratch = reinterpret_cast<double *>(base + off[11]);
+    p->dStatus = reinterpret_cast<int *>(base + off[12]);
+    SYLT_TRY(hipMemset(p->dStatus, 0, std::max(1, N) * sizeof(int)));
     return plan_sweep(*p);
 }
 
@@ -547,6 +582,48 @@ int check_ptrs(int N, const double *const *P)
     return SYLT_OK;
 }
 
+// Device-side phase timing for sylt_info: events recorded on the solve's
+// stream at phase boundaries; inert when not requested.
+class PhaseTimer {
+  public:
+    static constexpr int kMax = 8;
+    PhaseTimer(bool on, hipStream_t s) : on_(on), s_(s)
+    {
+        for (int i = 0; on_ && i < kMax; ++i)
+            if (hipEventCreate(&ev_[i]) != hipSuccess) {
+                ok_ = false;
+                n_ = i;
+                on_ = false;
+                return;
+            }
+        if (on_) n_ = kMax;
+    }
+    ~PhaseTimer()
+    {
+        for (int i = 0; i < n_; ++i) (void)hipEventDestroy(ev_[i]);
+    }
+    void reset() { used_ = 0; }
+    void mark()
+    {
+        if (on_ && used_ < kMax && hipEventRecord(ev_[used_++], s_) != hipSuccess) ok_ = false;
+    }
+    // milliseconds between marks i and i + 1 (after the stream has synchronised)
+    float span(int i)
+    {
+        float ms = 0.0f;
+        if (!on_ || i + 1 >= used_) return 0.0f;
+        if (hipEventElapsedTime(&ms, ev_[i], ev_[i + 1]) != hipSuccess) ok_ = false;
+        return ms;
+    }
+
+  private:
+    bool on_;
+    hipStream_t s_;
+    hipEvent_t ev_[kMax] = {};
+    int n_ = 0, used_ = 0;
+    bool ok_ = true;
+};
+
 int64_t mixed_workspace(const sylt_plan_s *p)
 {
     const int64_t r64 = residual_pass_count(*p) > 1 ? p->ntot * (int64_t)sizeof(double2) : 0;
@@ -557,7 +634,7 @@ int64_t mixed_workspace(const sylt_plan_s *p)
 
 extern "C" {
 
-int sylt_version(void) { return 101; }
+int sylt_version(void) { return 200; }
 
 const char *sylt_status_string(int code)
 {
@@ -574,7 +651,8 @@ const char *sylt_status_string(int code)
     }
 }
 
-int sylt_schur_factor(int N, const int64_t *n, const double *const *A, void *stream, sylt_plan *out)
+int sylt_schur_factor_ex(int N, const int64_t *n, const double *const *A, int qr_iter_per_n,
+                         void *stream, sylt_plan *out)
 {
     if (!out) return SYLT_E_INVALID_ARG;
     *out = nullptr;
@@ -590,7 +668,8 @@ int sylt_schur_factor(int N, const int64_t *n, const double *const *A, void *str
             st = status_of(hipMemcpyAsync(p->dA + p->moff[k], A[k], n[k] * n[k] * sizeof(double2),
                                           hipMemcpyDeviceToDevice, s));
     }
-    if (!st) st = status_of(launch_schur(*p, kSchurIterPerN, s));
+    if (!st)
+        st = status_of(launch_schur(*p, qr_iter_per_n > 0 ? qr_iter_per_n : kSchurIterPerN, s));
     p->has_A = true;
     if (!st) st = finish_plan(p, s, true);
     if (st) {
@@ -598,6 +677,31 @@ int sylt_schur_factor(int N, const int64_t *n, const double *const *A, void *str
         return st;
     }
     *out = p;
+    return SYLT_OK;
+}
+
+int sylt_schur_factor(int N, const int64_t *n, const double *const *A, void *stream, sylt_plan *out)
+{
+    return sylt_schur_factor_ex(N, n, A, 0, stream, out);
+}
+
+int sylt_plan_set_sweep_blocks(sylt_plan p, int M, const int *blocks)
+{
+    if (!p || !blocks || M != p->M) return SYLT_E_INVALID_ARG;
+    if (M == 0) return SYLT_OK;
+    // validate on a copy first so that a rejected request leaves the plan as it was
+    for (int j = 0; j < M; ++j)
+        if (blocks[j] < 1 || blocks[j] > p->cdim[j]) return SYLT_E_INVALID_ARG;
+    SYLT_TRY(hipDeviceSynchronize());  // earlier calls may still read the old tables
+    sylt::SweepPlan old = p->sweep;
+    p->sweep = sylt::SweepPlan{};
+    int st = plan_sweep(*p, blocks);
+    if (st) {
+        free_sweep_tables(p->sweep);
+        p->sweep = old;
+        return st;
+    }
+    free_sweep_tables(old);
     return SYLT_OK;
 }
 
@@ -672,7 +776,8 @@ int sylt_plan_describe(sylt_plan p, char *buf, size_t len)
         s += "]";
     };
     passes("transform_passes", p->passes);
-    passes("residual_passes", p->rpasses);
+    passes("residual_passes", p->residual_mfma ? p->mrpasses : p->rpasses);
+    s += std::string(",\"residual_form\":\"") + (p->residual_mfma ? "mfma" : "valu") + "\"";
     const SweepDesc &sd = p->sweep.desc;
     int launches = 0;
     for (size_t l = 0; l + 1 < p->sweep.level_off.size(); ++l)
@@ -753,18 +858,28 @@ int sylt_solve(sylt_plan p, const sylt_opts *o, const double *B, double *X, void
         info->iterations = 0;
         info->rel_residual = -1.0;
         info->sep = p->sep;
+        info->ms_transform = info->ms_sweep = info->ms_residual = 0.0f;
     }
+    // per-phase device times, only when info is requested
+    PhaseTimer tm(info != nullptr, s);
     if (precision == SYLT_FP64) {
+        tm.mark();
         SYLT_TRY(launch_transform_from(*p, SYLT_TO_SCHUR, Bc, Xc, s));
+        tm.mark();
         SYLT_TRY(launch_sweep(*p, SYLT_OP_N, SYLT_FP64, Xc, s));
+        tm.mark();
         SYLT_TRY(launch_transform(*p, SYLT_FROM_SCHUR, SYLT_FP64, Xc, s));
+        tm.mark();
         if (info) {
             info->iterations = 1;
             SYLT_TRY(hipStreamSynchronize(s));
+            info->ms_transform = tm.span(0) + tm.span(2);
+            info->ms_sweep = tm.span(1);
         }
         return SYLT_OK;
     }
-    // MIXED: iterative refinement with FP32 transforms
+    // MIXED: iterative refinement with FP32 transforms.  B is read by every
+    // residual, so X must not alias it.
     if (!p->has_A || p->M == 0 || Xc == Bc || o->max_iter < 1 || !(o->rtol >= 0.0))
         return SYLT_E_INVALID_ARG;
     if (!ws || (int64_t)ws_bytes < mixed_workspace(p)) return SYLT_E_WORKSPACE;
@@ -780,16 +895,27 @@ int sylt_solve(sylt_plan p, const sylt_opts *o, const double *B, double *X, void
     int it = 0;
     double rel = -1.0;
     int st = SYLT_E_NO_CONVERGENCE;
+    float ms_tr = 0.0f, ms_sw = 0.0f, ms_res = 0.0f;
     for (;;) {
+        tm.reset();
+        tm.mark();
         SYLT_TRY(launch_transform(*p, SYLT_TO_SCHUR, SYLT_MIXED, R32, s));
+        tm.mark();
         SYLT_TRY(launch_sweep(*p, SYLT_OP_N, SYLT_MIXED, R32, s));
+        tm.mark();
         SYLT_TRY(launch_transform(*p, SYLT_FROM_SCHUR, SYLT_MIXED, R32, s));
+        tm.mark();
         SYLT_TRY(launch_axpy_c64(Xc, R32, p->ntot, it == 0, s));
         ++it;
+        tm.mark();
         SYLT_TRY(launch_residual(*p, Bc, Xc, R64, R32, d_norms, s));
+        tm.mark();
         double nrm[2];
         SYLT_TRY(hipMemcpyAsync(nrm, d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         SYLT_TRY(hipStreamSynchronize(s));
+        ms_tr += tm.span(0) + tm.span(2);
+        ms_sw += tm.span(1);
+        ms_res += tm.span(4);
         rel = nrm[1] > 0.0 ? std::sqrt(nrm[0] / nrm[1]) : std::sqrt(nrm[0]);
         if (rel <= o->rtol) {
             st = SYLT_OK;
@@ -801,6 +927,9 @@ int sylt_solve(sylt_plan p, const sylt_opts *o, const double *B, double *X, void
         info->status = st;
         info->iterations = it;
         info->rel_residual = rel;
+        info->ms_transform = ms_tr;
+        info->ms_sweep = ms_sw;
+        info->ms_residual = ms_res;
     }
     return st;
 }

@@ -39,6 +39,11 @@ __device__ __forceinline__ double rsqrt_nr(double x)
     return y;
 }
 
+// FAST selects the reciprocal-square-root form for moduli in range (the
+// large-extent kernel, where the rotation sits on the critical path of every
+// QR step); the LDS kernel for n <= 64 keeps the hypot form, whose c and s are
+// each within about one rounding of a unitary rotation.
+template <bool FAST>
 __device__ __forceinline__ void givens(double2 a, double2 b, double &c, double2 &s)
 {
     // [c s; -conj(s) c] [a; b] = [r; 0] with real c and c^2 + |s|^2 = 1
@@ -58,10 +63,16 @@ __device__ __forceinline__ void givens(double2 a, double2 b, double &c, double2 
     // two independent reciprocal square roots of the sums of squares (a short
     // dependence chain: this sits on the critical path of a QR sweep)
     const double aa = a.x * a.x + a.y * a.y, bb = b.x * b.x + b.y * b.y;
-    if (aa > 0x1p-960 && aa < 0x1p960 && bb > 0x1p-960 && bb < 0x1p960) {
+    if (FAST && aa > 0x1p-960 && aa < 0x1p960 && bb > 0x1p-960 && bb < 0x1p960) {
         const double w = rsqrt_nr(aa) * rsqrt_nr(aa + bb);
         c = aa * w;
         s = cscale(cmul(a, cconj(b)), w);
+        // one first-order step towards c^2 + |s|^2 = 1: the products above
+        // carry a few roundings each, and a rotation that is not unitary to
+        // rounding lets U drift from unitarity over many QR sweeps
+        const double g = fma(-0.5, fma(c, c, fma(s.x, s.x, s.y * s.y)), 1.5);
+        c *= g;
+        s = cscale(s, g);
         return;
     }
     const double absa = cabs2(a), absb = cabs2(b);
@@ -148,7 +159,7 @@ __device__ __forceinline__ int qr_block(double2 *H, double2 *Q, int n, int tid, 
             __syncthreads();
             double c;
             double2 s;
-            givens(slot[0], slot[1], c, s);
+            givens<true>(slot[0], slot[1], c, s);
             if (tid == 0) {
                 gc[k] = c;
                 gs[k] = s;
@@ -381,7 +392,7 @@ __global__ void __launch_bounds__(NT) schur_kernel(SchurJobs jobs, const double2
         for (int k = lo; k < hi; ++k) {
             double c;
             double2 s;
-            givens(HH(k, k), HH(k + 1, k), c, s);
+            givens<GLOBAL>(HH(k, k), HH(k + 1, k), c, s);
             if (tid == 0) {
                 gc[k] = c;
                 gs[k] = s;

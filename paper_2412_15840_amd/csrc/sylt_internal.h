@@ -162,6 +162,7 @@ struct SweepPlan {
     int *d_llist = nullptr;          // local entries sorted by local level
     int *d_lloff = nullptr;          // local level offsets
     int *d_lanetab = nullptr;        // [round][lane] packed local-solve work items
+    void *arena = nullptr;           // the one device allocation holding the tables above
     size_t lds_bytes = 0;
 };
 
@@ -196,6 +197,7 @@ struct sylt_plan_s {
     float2 *dUh32 = nullptr;
     int *dStatus = nullptr;          // per-mode Schur status
     double *dScratch = nullptr;      // small reduction scratch (plan-owned)
+    void *arena = nullptr;           // the one device allocation holding the buffers above
     size_t scratch_bytes = 0;
     double sep = 0.0;
     std::vector<sylt::PassDesc> passes;   // transform passes (one LDS tile)
@@ -260,7 +262,10 @@ size_t grad_A_workspace(const sylt_plan_s &p);
 
 // planning (api.cpp)
 void plan_passes(sylt_plan_s &p);
-int plan_sweep(sylt_plan_s &p);
+// block sizes of the sweep tiles: chosen by the cost model when force_b is
+// null, else force_b[j] for every compressed mode j (validated)
+int plan_sweep(sylt_plan_s &p, const int *force_b = nullptr);
+void free_sweep_tables(SweepPlan &sp);
 size_t max_lds_bytes();
 
 }  // namespace sylt

@@ -5,7 +5,8 @@ Low-level functions mirror the C ABI in include/sylt.h one to one and take
 flat, contiguous CUDA tensors holding column-major data (mode 1 fastest, the
 paper's linear index, Section 2.2 eq. e:index):
 
-    Plan.factor(n, A)                 sylt_schur_factor
+    Plan.factor(n, A)                 sylt_schur_factor_ex
+    Plan.set_sweep_blocks(blocks)     sylt_plan_set_sweep_blocks
     Plan.from_factors(n, U, T, A)     sylt_plan_from_factors
     transform(plan, X, direction)     sylt_transform
     sweep(plan, CY, op)               sylt_sweep
@@ -55,7 +56,9 @@ class _Opts(ctypes.Structure):
 
 class _Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int),
-                ("rel_residual", ctypes.c_double), ("sep", ctypes.c_double)]
+                ("rel_residual", ctypes.c_double), ("sep", ctypes.c_double),
+                ("ms_transform", ctypes.c_float), ("ms_sweep", ctypes.c_float),
+                ("ms_residual", ctypes.c_float)]
 
 
 def lib():
@@ -67,6 +70,9 @@ def lib():
                                f"`python -c 'import __graft_entry__ as g; g.build()'`")
         L = ctypes.CDLL(LIB_PATH)
         L.sylt_schur_factor.argtypes = [ctypes.c_int, _i64p, _vp, _vp, ctypes.POINTER(_vp)]
+        L.sylt_schur_factor_ex.argtypes = [ctypes.c_int, _i64p, _vp, ctypes.c_int, _vp,
+                                           ctypes.POINTER(_vp)]
+        L.sylt_plan_set_sweep_blocks.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.sylt_plan_from_factors.argtypes = [ctypes.c_int, _i64p, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]
         L.sylt_plan_get_factors.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
         L.sylt_plan_separation.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
@@ -139,12 +145,21 @@ class Plan:
             self.ntot *= v
 
     @classmethod
-    def factor(cls, n, A_list, stream=None):
+    def factor(cls, n, A_list, stream=None, qr_iter_per_n=0):
+        """sylt_schur_factor_ex; qr_iter_per_n <= 0 keeps the default QR cap."""
         A = [_colmajor(a) for a in A_list]
         h = ctypes.c_void_p()
-        _check(lib().sylt_schur_factor(len(n), _dims(n), ctypes.cast(_ptrs(A), _vp),
-                                       _stream(stream), ctypes.byref(h)), "sylt_schur_factor")
+        _check(lib().sylt_schur_factor_ex(len(n), _dims(n), ctypes.cast(_ptrs(A), _vp),
+                                          int(qr_iter_per_n), _stream(stream), ctypes.byref(h)),
+               "sylt_schur_factor_ex")
         return cls(h, n)
+
+    def set_sweep_blocks(self, blocks):
+        """sylt_plan_set_sweep_blocks: block sizes of the non-singleton modes."""
+        arr = (ctypes.c_int * max(1, len(blocks)))(*[int(b) for b in blocks])
+        _check(lib().sylt_plan_set_sweep_blocks(self.handle, len(blocks), arr),
+               "sylt_plan_set_sweep_blocks")
+        return self
 
     @classmethod
     def from_factors(cls, n, U_list, T_list, A_list=None, stream=None):
@@ -227,7 +242,8 @@ def residual(plan, B, X, out=None, stream=None):
 
 def solve(plan, B, precision="fp64", rtol=1e-12, max_iter=8, out=None, workspace=None,
           stream=None, info=False):
-    """X with sum_k A_k x_k X = B for flat complex128 B (out may be B)."""
+    """X with sum_k A_k x_k X = B for flat complex128 B (out may be B for
+    FP64; the MIXED form rejects out aliasing B, which every residual re-reads)."""
     _flat(B, torch.complex128)
     X = out if out is not None else torch.empty_like(B)
     prec = _PREC[precision]
@@ -244,7 +260,9 @@ def solve(plan, B, precision="fp64", rtol=1e-12, max_iter=8, out=None, workspace
     _check(code, "sylt_solve")
     if info:
         return X, {"status": inf.status, "iterations": inf.iterations,
-                   "rel_residual": inf.rel_residual, "sep": inf.sep}
+                   "rel_residual": inf.rel_residual, "sep": inf.sep,
+                   "ms_transform": inf.ms_transform, "ms_sweep": inf.ms_sweep,
+                   "ms_residual": inf.ms_residual}
     return X
 
 

@@ -40,7 +40,7 @@ def test_status_strings(L):
         s = L.sylt_status_string(code)
         assert s and s != b"unknown status"
     assert L.sylt_status_string(5) == b"unknown status"
-    assert L.sylt_version() == 101
+    assert L.sylt_version() == 200
 
 
 def _dims(n):
@@ -83,6 +83,20 @@ def test_null_pointers_rejected(L):
     assert L.sylt_evolve(None, ctypes.c_double(0.1), None, None, None, None, 0, None) == -1
     L.sylt_evolve_workspace_bytes.restype = ctypes.c_int64
     assert L.sylt_evolve_workspace_bytes(None) == -1
+    assert L.sylt_schur_factor_ex(2, _dims([2, 2]), None, 1, None, ctypes.byref(h)) == -1
+    blocks = (ctypes.c_int * 2)(2, 2)
+    assert L.sylt_plan_set_sweep_blocks(None, 2, blocks) == -1
+
+
+def test_info_struct_layout_matches_header():
+    """sylt_info as declared in the header and as marshalled by the binding."""
+    from paper_2412_15840_amd import sylt
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\} sylt_info;", text).group(1)
+    names = re.findall(r"([a-z_]+)\s*[,;]", body)
+    assert [f[0] for f in sylt._Info._fields_] == names
+    assert ctypes.sizeof(sylt._Info) == 40
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

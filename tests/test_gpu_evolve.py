@@ -45,7 +45,7 @@ def _gpu_evolve(n, A, b, x0, t, out=None):
     ((5, 3, 7, 1, 9), 0.2),            # singleton mode, ragged tiles
     ((2, 3, 4, 5, 6, 7, 8), 0.1),      # the paper's N = 7 test sizes and time
     ((16, 16, 16), 0.05),
-    ((19, 19, 19, 19), 0.1),           # several sweep tiles, pencil local solve
+    ((19, 19, 19, 19), 0.1),           # several sweep tiles (blocks 19,7,7,7), packed local solve
     ((4,), 0.7),                       # N = 1
     ((3, 1, 1, 4), -0.2),              # negative time, two singletons
 ])

@@ -221,6 +221,23 @@ int sylt_solve_backward(sylt_plan p, const double *X, const double *GX, double *
                         double *const *GA, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * sylt_solve_backward_noalloc -- sylt_solve_backward for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): no workspace argument, and no hipMalloc,
+ * hipFree or allocating library call.  The grad-A partial sums go to a fixed
+ * 8 MiB scratch array that the library holds on every device it runs on
+ * until the process ends; its device address is looked up once per device.
+ * Same arguments, layout and results as sylt_solve_backward (results agree
+ * to rounding; with large n_k the partial sums use fewer workgroups).
+ * Calls on one device share that scratch: calls that overlap on one GPU (on
+ * different streams, or from different threads) race; order them.
+ * Errors: INVALID_ARG (null pointer), UNSUPPORTED (an n_k x n_k matrix of
+ * partial sums would not fit the scratch), DEVICE.
+ */
+int sylt_solve_backward_noalloc(sylt_plan p, const double *X, const double *GX, double *GB,
+                                double *const *GA, void *stream);
+
+/*
  * sylt_evolve -- time evolution by Theorem 1 in Schur form (eqs.
  * e:sylvesterNDG and e:G, from the proof's exp(tA) of a Kronecker sum): the
  * value at time t of the solution of X_t = sum_k A_k x_k X + B, X(0) = X0.

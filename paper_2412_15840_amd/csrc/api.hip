@@ -969,6 +969,34 @@ int sylt_evolve(sylt_plan p, double t, const double *B, const double *X0, double
     return SYLT_OK;
 }
 
+int sylt_solve_backward_noalloc(sylt_plan p, const double *X, const double *GX, double *GB,
+                                double *const *GA, void *stream)
+{
+    if (!p || !X || !GX || !GB) return SYLT_E_INVALID_ARG;
+    void *scr = nullptr;
+    size_t scr_bytes = 0;
+    bool any = false;
+    if (GA)
+        for (int k = 0; k < p->N; ++k) any |= GA[k] != nullptr;
+    if (any) {
+        // the grad-A partial sums live in the fixed scratch; one n_k x n_k
+        // matrix must fit (always true for n_k <= 256 and 8 MiB)
+        SYLT_TRY(noalloc_scratch(&scr, &scr_bytes));
+        for (int k = 0; k < p->N; ++k)
+            if (GA[k] && (size_t)p->n[k] * p->n[k] * sizeof(double2) > scr_bytes)
+                return SYLT_E_UNSUPPORTED;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double2 *G = reinterpret_cast<double2 *>(GB);
+    SYLT_TRY(launch_transform_from(*p, SYLT_TO_SCHUR, reinterpret_cast<const double2 *>(GX), G, s));
+    SYLT_TRY(launch_sweep(*p, SYLT_OP_C, SYLT_FP64, G, s));
+    SYLT_TRY(launch_transform(*p, SYLT_FROM_SCHUR, SYLT_FP64, G, s));
+    if (any)
+        SYLT_TRY(launch_grad_A(*p, G, reinterpret_cast<const double2 *>(X),
+                               reinterpret_cast<double2 *const *>(GA), scr, scr_bytes, s));
+    return SYLT_OK;
+}
+
 int sylt_solve_backward(sylt_plan p, const double *X, const double *GX, double *GB,
                         double *const *GA, void *ws, size_t ws_bytes, void *stream)
 {

@@ -2,7 +2,41 @@
 // conversions / updates and the grad-A contraction.
 #include "sylt_internal.h"
 
+#include <mutex>
+
+// Fixed device memory for the entry point that allocates nothing
+// (sylt_solve_backward_noalloc): the grad-A partial sums.  Every device the
+// library runs on holds its own copy until the process ends.  In host code
+// this name is only a stand-in for the symbol: the device address comes from
+// hipGetSymbolAddress (noalloc_scratch below) and is the only form of it that
+// reaches a kernel or a memory call.
+static __device__ __align__(256) unsigned char scratch[sylt::kNoAllocScratchBytes];
+
 namespace sylt {
+
+hipError_t noalloc_scratch(void **ptr, size_t *bytes)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        // once per device, with that device current: its copy of the array
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = kNoAllocScratchBytes;
+    return hipSuccess;
+}
+
 namespace {
 
 constexpr int kThreads = 256;
@@ -241,11 +275,18 @@ size_t grad_A_workspace(const sylt_plan_s &p)
     return need;
 }
 
+// The partial sums take blocks * n^2 entries; with a buffer smaller than
+// grad_A_workspace the stage-1 grid shrinks to what fits (each workgroup then
+// walks more chunks).  A buffer below one n x n matrix is rejected.
 hipError_t launch_grad_A(const sylt_plan_s &p, const double2 *G, const double2 *X, double2 *const *GA,
                          void *ws, size_t ws_bytes, hipStream_t s)
 {
-    if (ws_bytes < grad_A_workspace(p)) return hipErrorInvalidValue;
     double2 *partial = static_cast<double2 *>(ws);
+    for (int k = 0; k < p.N; ++k) {
+        if (!GA[k]) continue;
+        const int n = (int)p.n[k];
+        if (ws_bytes < (size_t)n * n * sizeof(double2)) return hipErrorInvalidValue;
+    }
     for (int k = 0; k < p.N; ++k) {
         if (!GA[k]) continue;
         const int n = (int)p.n[k];
@@ -253,7 +294,8 @@ hipError_t launch_grad_A(const sylt_plan_s &p, const double2 *G, const double2 *
         for (int j = 0; j < k; ++j) L *= p.n[j];
         for (int j = k + 1; j < p.N; ++j) R *= p.n[j];
         const int FB = grad_fibres_per_block(n);
-        const int64_t blocks = grad_blocks(L * R, n);
+        const int64_t fit = (int64_t)(ws_bytes / ((size_t)n * n * sizeof(double2)));
+        const int64_t blocks = std::min(grad_blocks(L * R, n), fit);
         const size_t lds = (size_t)2 * FB * n * sizeof(double2);
         hipLaunchKernelGGL(grad_partial_kernel, dim3((unsigned)blocks), dim3(kThreads), lds, s, G, X,
                            L, n, R, FB, partial);

@@ -22,6 +22,7 @@ constexpr int kSweepMaxRounds = 32;   // local-solve rounds held per lane in reg
 constexpr int kSweepPencilMax = 20;   // longest mode-0 pencil held in one lane's registers
 constexpr int kSweepPencilModes = 8;  // most tiled modes of the pencil form
 constexpr int kResidualMfmaCap = 4096;  // tile entries of the matrix-core residual pass
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;  // fixed device scratch per device
 
 // ----------------------------------------------------------------- complex
 // double2 / float2 hold (re, im).  All products are written as explicit fused
@@ -258,6 +259,9 @@ hipError_t launch_convert_c128_c64(float2 *out, const double2 *in, int64_t n, hi
 hipError_t launch_copy_c128(double2 *out, const double2 *in, int64_t n, hipStream_t s);
 hipError_t launch_grad_A(const sylt_plan_s &p, const double2 *G, const double2 *X, double2 *const *GA,
                          void *ws, size_t ws_bytes, hipStream_t s);
+// device address and size of the library's fixed scratch on the current
+// device (looked up once per device)
+hipError_t noalloc_scratch(void **ptr, size_t *bytes);
 size_t grad_A_workspace(const sylt_plan_s &p);
 
 // planning (api.cpp)

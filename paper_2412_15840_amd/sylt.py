@@ -13,6 +13,7 @@ paper's linear index, Section 2.2 eq. e:index):
     residual(plan, B, X)              sylt_residual
     solve(plan, B)                    sylt_solve
     solve_backward(plan, X, GX)       sylt_solve_backward
+    solve_backward_noalloc(...)       sylt_solve_backward_noalloc
     evolve(plan, t, B, X0)            sylt_evolve
 
 Matrices passed to / returned from these functions are ordinary (n, n) torch
@@ -85,6 +86,7 @@ def lib():
         L.sylt_solve.argtypes = [_vp, ctypes.POINTER(_Opts), _vp, _vp, _vp, ctypes.c_size_t, _vp,
                                  ctypes.POINTER(_Info)]
         L.sylt_solve_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+        L.sylt_solve_backward_noalloc.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
         L.sylt_evolve.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.sylt_evolve_workspace_bytes.argtypes = [_vp]
         L.sylt_evolve_workspace_bytes.restype = ctypes.c_int64
@@ -280,6 +282,20 @@ def solve_backward(plan, X, GX, want_A=True, out=None, stream=None):
            "sylt_solve_backward")
     GA = [_from_colmajor(g, nk) for g, nk in zip(GA_bufs, plan.n)] if want_A else None
     return GB, GA
+
+
+def solve_backward_noalloc(plan, X, GX, GB, GA_bufs=None, stream=None):
+    """sylt_solve_backward_noalloc into caller-allocated outputs: GB (flat
+    complex128 like GX) and GA_bufs, a list of flat n_k*n_k complex128 buffers
+    receiving column-major dL/dA_k (or None).  Allocates nothing."""
+    _flat(X, torch.complex128)
+    _flat(GX, torch.complex128)
+    _flat(GB, torch.complex128)
+    ptrs = ctypes.cast(_ptrs(GA_bufs), _vp) if GA_bufs is not None else None
+    _check(lib().sylt_solve_backward_noalloc(plan.handle, X.data_ptr(), GX.data_ptr(),
+                                             GB.data_ptr(), ptrs, _stream(stream)),
+           "sylt_solve_backward_noalloc")
+    return GB
 
 
 # ----------------------------------------------------------- torch facing

@@ -188,6 +188,7 @@ void free_sweep_tables(SweepPlan &sp)
     sp.d_llist = nullptr;
     sp.d_lloff = nullptr;
     sp.d_lanetab = nullptr;
+    sp.d_cst = nullptr;
     sp.level_off.clear();
 }
 
@@ -413,6 +414,23 @@ int plan_sweep(sylt_plan_s &p, const int *force_b)
             sd.rounds = 0;
         }
     }
+    // cross-section tables of the pull phase: for mode j, position c (the
+    // mixed-radix digits over the other modes, fastest first) -> the local
+    // entry with those digits and loc_j = 0
+    std::vector<int> cst;
+    for (int j = 0; j < M; ++j) {
+        sd.csoff[j] = (int)cst.size();
+        const int cs = (int)(S / b[j]);
+        for (int c = 0; c < cs; ++c) {
+            int rem = c, t0 = 0;
+            for (int i = 0; i < M; ++i) {
+                if (i == j || b[i] == 1) continue;
+                t0 += (rem % b[i]) * sd.ls[i];
+                rem /= b[i];
+            }
+            cst.push_back(t0);
+        }
+    }
     // every table in one device allocation, filled by one host-to-device copy
     std::vector<std::pair<const void *, size_t>> parts = {
         {&sd, sizeof(SweepDesc)},
@@ -422,6 +440,7 @@ int plan_sweep(sylt_plan_s &p, const int *force_b)
         {llist.data(), S * sizeof(int)},
         {lloff.data(), (nll + 1) * sizeof(int)},
         {tiles.data(), std::max<int64_t>(1, ntiles) * sizeof(int)},
+        {cst.data(), cst.size() * sizeof(int)},
     };
     if (ntiles == 0) parts.back().first = nullptr;
     std::vector<size_t> off(parts.size());
@@ -443,6 +462,7 @@ int plan_sweep(sylt_plan_s &p, const int *force_b)
     sp.d_llist = reinterpret_cast<int *>(base + off[4]);
     sp.d_lloff = reinterpret_cast<int *>(base + off[5]);
     sp.d_tiles = reinterpret_cast<int *>(base + off[6]);
+    sp.d_cst = reinterpret_cast<int *>(base + off[7]);
     SYLT_TRY(hipMemcpy(base, staging.data(), total, hipMemcpyHostToDevice));
     return SYLT_OK;
 }

@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
     const SweepDesc *__restrict__ sdp,
     const int *__restrict__ tiles, const int64_t *__restrict__ goff,
     const uint64_t *__restrict__ code, const int *__restrict__ llist,
-    const int *__restrict__ lloff, const int *__restrict__ lanetab)
+    const int *__restrict__ lloff, const int *__restrict__ lanetab, const int *__restrict__ cst)
 {
     // the descriptor is read from device memory: a by-value kernel argument
     // that lambdas capture would be copied to scratch
@@ -194,23 +194,14 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
         const int64_t sj = sd.s[j];
         const int cs = sd.S / b;
         const double2 *Tj = Tbuf + sd.moff[j];
+        const int *cj = cst + sd.csoff[j];
         for (int c = threadIdx.x; c < cs; c += blockDim.x) {
-            // cross-section position c -> local entry t0 (loc_j = 0) and its
-            // global offset, by mixed-radix digits over the other tiled modes
-            int rem = c, t0 = 0;
-            int64_t g0 = ts.base;
-            bool ok = true;
-#pragma unroll
-            for (int i = 0; i < M; ++i) {
-                const int bi = sd.b[i];
-                if (i == j || bi == 1) continue;
-                const int loc = rem % bi;
-                rem /= bi;
-                t0 += loc * sd.ls[i];
-                g0 += (int64_t)loc * sd.s[i];
-                ok &= loc < ts.e[i];
-            }
-            if (!ok) continue;
+            // cross-section position c -> local entry t0 (loc_j = 0), from the
+            // plan's table; its global offset and, in a ragged tile, whether
+            // it lies inside the tile, from the per-entry tables
+            const int t0 = cj[c];
+            if (ts.ragged && !entry_ok<MC>(code[t0], sd, ts)) continue;
+            const int64_t g0 = ts.base + goff[t0];
             double2 acc[kBmax];
 #pragma unroll
             for (int r = 0; r < kBmax; ++r) acc[r] = make_double2(0.0, 0.0);
@@ -257,11 +248,11 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
             den = cadd(den, ADJ ? cconj(lam) : lam);
             if (ADJ) {
                 for (int q = 1; q <= loc; ++q)
-                    num = csub(num, cmul(cconj(Td[(loc - q) + b * loc]), tile[t - q * lsj]));
+                    num = cmsub_conj(num, Td[(loc - q) + b * loc], tile[t - q * lsj]);
             } else {
                 const int qmax = ts.e[j] - 1 - loc;
                 for (int q = 1; q <= qmax; ++q)
-                    num = csub(num, cmul(Td[loc + b * (loc + q)], tile[t + q * lsj]));
+                    num = cmsub(num, Td[loc + b * (loc + q)], tile[t + q * lsj]);
             }
         }
         tile[t] = cdiv(num, den);
@@ -325,7 +316,7 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
             double2 num = tile[t];
             if (ADJ) {
 #pragma unroll
-                for (int kk = 0; kk < K; ++kk) num = csub(num, cmul(cconj(cf[kk]), y[kk]));
+                for (int kk = 0; kk < K; ++kk) num = cmsub_conj(num, cf[kk], y[kk]);
             } else {
                 // past the block end y is zero; the coefficient index stays in it
 #pragma unroll
@@ -333,7 +324,7 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
                     if (kb >= e0) break;  // uniform
 #pragma unroll
                     for (int kk = kb; kk < kb + kChunk0; ++kk)
-                        if (kk > K) num = csub(num, cmul(cf[min(kk, e0 - 1)], y[kk]));
+                        if (kk > K) num = cmsub(num, cf[min(kk, e0 - 1)], y[kk]);
                 }
             }
             double2 yk = make_double2(0.0, 0.0);
@@ -345,7 +336,7 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
                     if (i >= 2 * (M - 1)) break;
                     const double2 a = tdiag[dep[i] >> 16];
                     const double2 yn = tile[ADJ ? t - (dep[i] & 0xffff) : t + (dep[i] & 0xffff)];
-                    num = csub(num, ADJ ? cmul(cconj(a), yn) : cmul(a, yn));
+                    num = ADJ ? cmsub_conj(num, a, yn) : cmsub(num, a, yn);
                 }
                 if (sd.pen_long) {  // neighbours beyond the second (blocks longer than 3)
 #pragma unroll 1
@@ -356,8 +347,8 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
                         const double2 *Td = tdiag + sd.tdoff[j];
                         const int nq = ADJ ? loc : ts.e[j] - 1 - loc;
                         for (int q = 3; q <= nq; ++q)
-                            num = ADJ ? csub(num, cmul(cconj(Td[(loc - q) + b * loc]), tile[t - q * lsj]))
-                                      : csub(num, cmul(Td[loc + b * (loc + q)], tile[t + q * lsj]));
+                            num = ADJ ? cmsub_conj(num, Td[(loc - q) + b * loc], tile[t - q * lsj])
+                                      : cmsub(num, Td[loc + b * (loc + q)], tile[t + q * lsj]);
                     }
                 }
                 yk = cdiv_scaled(num, den);
@@ -460,7 +451,7 @@ hipError_t run_sweep_as(const sylt_plan_s &p, V *X, hipStream_t s)
         if (b1 <= b0) continue;
         hipLaunchKernelGGL(ker, dim3((unsigned)(b1 - b0)), dim3(kThreads), sp.lds_bytes, s, X,
                            p.dT, p.dTt, sp.d_desc, sp.d_tiles + b0, sp.d_goff, sp.d_code, sp.d_llist,
-                           sp.d_lloff, sp.d_lanetab);
+                           sp.d_lloff, sp.d_lanetab, sp.d_cst);
     }
     return hipGetLastError();
 }

@@ -53,6 +53,23 @@ __device__ __forceinline__ V cmac_conj(V acc, V a, V b)
     acc.y = fma(-a.y, b.x, acc.y);
     return acc;
 }
+// acc - a * b and acc - conj(a) * b as four fused multiply-adds
+__device__ __forceinline__ double2 cmsub(double2 acc, double2 a, double2 b)
+{
+    acc.x = fma(-a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(-a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
+__device__ __forceinline__ double2 cmsub_conj(double2 acc, double2 a, double2 b)
+{
+    acc.x = fma(-a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(-a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
 __host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __host__ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __host__ __device__ inline double2 cmul(double2 a, double2 b)
@@ -151,6 +168,7 @@ struct SweepDesc {
     int round_level[kSweepMaxRounds];  // local level of each round, ascending
     int nsing;                   // singleton modes: their scalars join every eigenvalue sum
     int64_t singoff[kMaxModes];  // offsets of those 1x1 T_k in the matrix buffer
+    int csoff[kMaxModes];        // offset of mode j's cross-section table (entries)
 };
 
 struct SweepPlan {
@@ -163,6 +181,7 @@ struct SweepPlan {
     int *d_llist = nullptr;          // local entries sorted by local level
     int *d_lloff = nullptr;          // local level offsets
     int *d_lanetab = nullptr;        // [round][lane] packed local-solve work items
+    int *d_cst = nullptr;            // per mode: cross-section position -> local entry at loc_j = 0
     void *arena = nullptr;           // the one device allocation holding the tables above
     size_t lds_bytes = 0;
 };

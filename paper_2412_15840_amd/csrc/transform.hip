@@ -171,6 +171,23 @@ __device__ __forceinline__ int fibre_base(const PassDesc &pa, const TileCoord &t
     return l + pa.lb * (glo + gs * n * ghi + (int)pa.G * r);
 }
 
+// Table of fibre_base over a full tile, for every mode of the pass: entry
+// q * (nfull) + f, nfull = lb * (G / n) * rb fibres per mode.  Built once per
+// workgroup so the per-group lookup is one LDS read instead of the divisions
+// of fibre_base; a ragged tile masks fibres with l >= lbe or beyond its rows.
+__device__ __forceinline__ void build_fibre_table(int *fbt, const PassDesc &pa, int n)
+{
+    const int nfull = pa.lb * (int)(pa.G / n) * pa.rb;
+    TileCoord full;
+    full.l0 = full.r0 = 0;
+    full.lbe = pa.lb;
+    full.rbe = pa.rb;
+    for (int idx = threadIdx.x; idx < pa.ng * nfull; idx += blockDim.x) {
+        const int q = idx / nfull, f = idx - q * nfull;
+        fbt[idx] = fibre_base(pa, full, q, n, f);
+    }
+}
+
 // ------------------------------------------------------------ transform
 // NN > 0: every mode of the group has extent NN.  NN == 0: mixed extents <= 24.
 template <typename V, int NN>
@@ -382,6 +399,10 @@ template <> struct MfmaT<double> {
     }
     // row of the 16-row block held by value v of lane l
     static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+    // block row r -> output (within the block's 8) and part (0 re, 1 im),
+    // ordered so that values 2c and 2c + 1 of a lane are one complex output
+    static __device__ __forceinline__ int out_of_row(int r) { return (r & 3) + 4 * (r >> 3); }
+    static __device__ __forceinline__ int part_of_row(int r) { return (r >> 2) & 1; }
 };
 template <> struct MfmaT<float> {
     using acc = mf_f4;
@@ -390,6 +411,8 @@ template <> struct MfmaT<float> {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
     static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+    static __device__ __forceinline__ int out_of_row(int r) { return r >> 1; }
+    static __device__ __forceinline__ int part_of_row(int r) { return r & 1; }
 };
 
 // two waves per SIMD; each lane prefetches 16 entries of the next tile
@@ -403,7 +426,7 @@ __global__ void __launch_bounds__(kMfmaThreads) transform_mfma_kernel(V *X, cons
 {
     using R = typename CTraits<V>::R;
     using MT = MfmaT<R>;
-    constexpr int RB = (2 * NN + 15) / 16;  // 16-row blocks of the real matrix
+    constexpr int RB = (NN + 7) / 8;        // 16-row blocks of the real matrix (8 outputs each)
     constexpr int KS = (2 * NN + 3) / 4;    // 4-column steps
     constexpr int WAVES = kMfmaThreads / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -417,22 +440,30 @@ __global__ void __launch_bounds__(kMfmaThreads) transform_mfma_kernel(V *X, cons
         const int l = idx & 63;
         const int frag = idx >> 6;
         const int kk = frag % KS, rb = (frag / KS) % RB, q = frag / (KS * RB);
-        const int row = 16 * rb + (l & 15), k = 4 * kk + (l >> 4);
-        const int i = row >> 1, m = k >> 1;
+        const int r = l & 15, k = 4 * kk + (l >> 4);
+        const int i = 8 * rb + MT::out_of_row(r), m = k >> 1;
         R v = 0;
         if (i < NN && m < NN) {
             const V c = Mbuf[pa.moff[q] + i + NN * m];
-            const int a = row & 1, b = k & 1;
+            const int a = MT::part_of_row(r), b = k & 1;
             v = a == b ? c.x : (a ? c.y : -c.y);
         }
         afr[idx] = v;
     }
+    int *fbt = reinterpret_cast<int *>(afr + pa.ng * RB * KS * 64);
+    build_fibre_table(fbt, pa, NN);
+    const int nfull = pa.lb * (int)(pa.G / NN) * pa.rb;
+    // one zero operand after the table: lanes outside the tile (or past the
+    // matrix edge) read it, so the operand loads need no branches
+    R *zslot = reinterpret_cast<R *>(fbt + ((pa.ng * nfull + 3) & ~3));
+    if (threadIdx.x == 0) zslot[0] = R(0);
+    const int zidx = (int)(zslot - reinterpret_cast<R *>(tile));
 
     R pre_re[kMfmaRegs], pre_im[kMfmaRegs];
     int64_t t = blockIdx.x;
     if (t >= ntiles) return;
-    // address of tile entry e (rb == 1 needs no division)
-    auto entry_addr = [&](const TileCoord &c, int e, bool &ok) -> int64_t {
+    // global address of tile entry e (rb == 1 needs no division)
+    auto gaddr = [&](const TileCoord &c, int e, bool &ok) -> int64_t {
         const int l = e & (pa.lb - 1);
         const int rest = e >> pa.lbshift;
         int g = rest, r = 0;
@@ -447,7 +478,7 @@ __global__ void __launch_bounds__(kMfmaThreads) transform_mfma_kernel(V *X, cons
 #pragma unroll
         for (int i = 0; i < kMfmaRegs; ++i) {
             bool ok;
-            const int64_t a = entry_addr(c, threadIdx.x + i * kMfmaThreads, ok);
+            const int64_t a = gaddr(c, threadIdx.x + i * kMfmaThreads, ok);
             if (ok) {
                 const V v = Xs[a];
                 pre_re[i] = v.x;
@@ -457,7 +488,11 @@ __global__ void __launch_bounds__(kMfmaThreads) transform_mfma_kernel(V *X, cons
     };
     TileCoord tc = tile_coord_of(pa, t);
     load_regs(tc);
+    // every path into the loop has the prefetch registers complete (here and
+    // before the last mode), so the refill never waits on result stores
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
     while (true) {
+        // this tile's entries (loaded during the previous tile) into LDS
 #pragma unroll
         for (int i = 0; i < kMfmaRegs; ++i) {
             const int e = threadIdx.x + i * kMfmaThreads;
@@ -470,58 +505,75 @@ __global__ void __launch_bounds__(kMfmaThreads) transform_mfma_kernel(V *X, cons
         const int64_t tn = t + gridDim.x;
         const TileCoord tcn = tile_coord_of(pa, tn < ntiles ? tn : t);
         if (tn < ntiles) load_regs(tcn);
-        for (int q = 0; q < pa.ng; ++q) {
+        // one mode of the pass: the products of all fibres of mode q, written
+        // back into LDS, or (the last mode) straight to memory
+        auto mode = [&](int q, bool last) __attribute__((always_inline)) {
             const R *aq = afr + q * RB * KS * 64 + lane;
             const int nfib = pa.lb * (int)(pa.G / NN) * tc.rbe;
             const int stride = pa.lb * pa.gs[q];
             const int ngroups = (nfib + 15) >> 4;
-            // B operand of a group of 16 fibres: each lane reads one real value
-            // per k-step; the k-step loop stays rolled (by two) so only a few
-            // operands are live, and the RB accumulator chains interleave
+            const int *fq = fbt + q * nfull;
             const R *tr = reinterpret_cast<const R *>(tile);
             for (int grp = wave; grp < ngroups; grp += WAVES) {
                 const int f = 16 * grp + (lane & 15);
-                const int base = f < nfib ? fibre_base(pa, tc, q, NN, f) : -1;
+                const int base = (f < nfib && (f & (pa.lb - 1)) < tc.lbe) ? fq[min(f, nfull - 1)] : -1;
                 const int kb = lane >> 4;  // k within a step
+                // all B operands of the group first (branch-free addresses),
+                // then the MFMA chain
+                R bv[KS];
+#pragma unroll
+                for (int kk = 0; kk < KS; ++kk) {
+                    const int k = 4 * kk + kb;
+                    const int m = k >> 1;
+                    const int idx = (base >= 0 && m < NN) ? 2 * (base + m * stride) + (k & 1) : zidx;
+                    bv[kk] = tr[idx];
+                }
                 typename MT::acc acc[RB];
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) acc[rb] = typename MT::acc{0, 0, 0, 0};
 #pragma unroll
                 for (int kk = 0; kk < KS; ++kk) {
-                    const int k = 4 * kk + kb;
-                    const int m = k >> 1;
-                    const R b = (base >= 0 && m < NN) ? tr[2 * (base + m * stride) + (k & 1)] : R(0);
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb)
-                        acc[rb] = MT::mma(aq[(rb * KS + kk) * 64], b, acc[rb]);
+                        acc[rb] = MT::mma(aq[(rb * KS + kk) * 64], bv[kk], acc[rb]);
                 }
                 __builtin_amdgcn_sched_barrier(0);
                 if (base >= 0) {
+                    // values (0, 1) and (2, 3) of a lane are two complex outputs
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int row = 16 * rb + MT::row(lane, v);
-                            const int i = row >> 1;
+                        for (int c = 0; c < 2; ++c) {
+                            const int i = 8 * rb + MT::out_of_row(MT::row(lane, 2 * c));
                             if (i < NN) {
-                                R *dst = reinterpret_cast<R *>(&tile[base + i * stride]);
-                                dst[row & 1] = acc[rb][v];
+                                V y;
+                                y.x = acc[rb][2 * c];
+                                y.y = acc[rb][2 * c + 1];
+                                const int e = base + i * stride;
+                                if (last) {
+                                    bool ok;
+                                    const int64_t a = gaddr(tc, e, ok);
+                                    X[a] = y;
+                                } else {
+                                    tile[e] = y;
+                                }
                             }
                         }
                     }
                 }
             }
+        };
+        for (int q = 0; q + 1 < pa.ng; ++q) {
+            mode(q, false);
             __syncthreads();
         }
-#pragma unroll
-        for (int i = 0; i < kMfmaRegs; ++i) {
-            const int e = threadIdx.x + i * kMfmaThreads;
-            bool ok;
-            const int64_t a = entry_addr(tc, e, ok);
-            if (ok) X[a] = tile[e];
-        }
+        // the next tile's loads are complete before the last mode, whose
+        // results go straight to memory: the LDS refill after it then does
+        // not wait on those stores
+        __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
+        mode(pa.ng - 1, true);
         if (tn >= ntiles) break;
-        __syncthreads();
+        __syncthreads();  // every wave has read the tile before the refill
         t = tn;
         tc = tcn;
     }
@@ -712,6 +764,9 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
         }
         afr[idx] = v;
     }
+    int *fbt = reinterpret_cast<int *>(afr + pa.ng * RB * KS * 64);
+    build_fibre_table(fbt, pa, NN);
+    const int nfull = pa.lb * (int)(pa.G / NN) * pa.rb;
     double2 shift = make_double2(0.0, 0.0);
     if (first)
         for (int i = 0; i < sing.count; ++i) shift = cadd(shift, Abuf[sing.off[i]]);
@@ -767,9 +822,10 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
             const int nfib = pa.lb * (int)(pa.G / NN) * tc.rbe;
             const int stride = pa.lb * pa.gs[q];
             const int ngroups = (nfib + 15) >> 4;
+            const int *fq = fbt + q * nfull;
             for (int grp = wave; grp < ngroups; grp += WAVES) {
                 const int f = 16 * grp + (lane & 15);
-                const int base = f < nfib ? fibre_base(pa, tc, q, NN, f) : -1;
+                const int base = (f < nfib && (f & (pa.lb - 1)) < tc.lbe) ? fq[f] : -1;
                 const int kb = lane >> 4;
                 typename MT::acc d[RB];
 #pragma unroll
@@ -842,6 +898,12 @@ __global__ void reduce_sum_kernel(const double *__restrict__ in, int64_t n, doub
     }
 }
 
+// LDS bytes of the fibre-base table of a matrix-core pass with extent n
+size_t fibre_table_bytes(const PassDesc &pa, int n)
+{
+    return n > 0 ? (size_t)pa.ng * (size_t)(pa.lb * (pa.G / n) * pa.rb) * sizeof(int) : 0;
+}
+
 int device_cus()
 {
     int dev = 0, cus = 0;
@@ -894,9 +956,9 @@ hipError_t run_transform_pass(const PassDesc &pa, V *X, const V *Xs, const V *Mb
         // if they do not fit next to the tile, the VALU variant runs instead
 #define SYLT_MFMA(NNV, PV)                                                                      \
     do {                                                                                        \
-        constexpr int RBv = (2 * NNV + 15) / 16, KSv = (2 * NNV + 3) / 4;                       \
-        const size_t ldsm =                                                                     \
-            lds + (size_t)pa.ng * RBv * KSv * 64 * sizeof(typename CTraits<V>::R);             \
+        constexpr int RBv = (NNV + 7) / 8, KSv = (2 * NNV + 3) / 4;                             \
+        const size_t ldsm = lds + (size_t)pa.ng * RBv * KSv * 64 * sizeof(typename CTraits<V>::R) + \
+                            fibre_table_bytes(pa, NNV) + 32;                                    \
         if (ldsm > max_lds) {                                                                   \
             SYLT_PIPE(NNV, PV);                                                                 \
             break;                                                                              \
@@ -972,7 +1034,7 @@ size_t residual_mfma_lds(const PassDesc &pa)
 {
     const int n = pa.uniform_n;
     const size_t frags = (size_t)pa.ng * ((2 * n + 15) / 16) * ((2 * n + 3) / 4) * 64;
-    return pa.lds_bytes(sizeof(double2)) * 2 + frags * sizeof(double);
+    return pa.lds_bytes(sizeof(double2)) * 2 + frags * sizeof(double) + fibre_table_bytes(pa, n);
 }
 
 hipError_t launch_transform_with(const sylt_plan_s &p, const double2 *M, double2 *X, hipStream_t s)

@@ -32,7 +32,6 @@ namespace {
 
 constexpr int kThreads = kSweepThreads;
 constexpr int kBmax = 8;   // largest block of a partially tiled mode
-constexpr int kPrefetch = 8;  // pulled entries loaded before they are used
 constexpr int kPen = kSweepPencilMax;  // pencil entries held in registers
 constexpr int kChunk0 = 4;    // mode-0 coefficients loaded together
 static_assert(kPen % kChunk0 == 0, "pencil length must be whole chunks");
@@ -95,6 +94,55 @@ __device__ __forceinline__ bool entry_ok(uint64_t c, const SweepDesc &sd, const 
         if (loc >= ts.e[j]) return false;
     }
     return true;
+}
+
+// Pull of one mode: for every cross-section position of the tile (one per
+// lane and round), the rows of the block receive
+//   sum over k outside the block of T_j[row, k] * Y[..., k, ...]
+// (k above the block for the upper sweep, below it for the adjoint).  BJ is
+// the block size, NP the loads a lane keeps in flight.
+template <typename V, bool ADJ, int MC, int BJ, int NP>
+__device__ __forceinline__ void pull_mode(const V *__restrict__ X, const double2 *__restrict__ Tj,
+                                          const int *__restrict__ cj,
+                                          const int64_t *__restrict__ goff,
+                                          const uint64_t *__restrict__ code, const SweepDesc &sd,
+                                          const TileState &ts, double2 *tile, int o, int e, int d,
+                                          int k0, int k1, int lsj, int64_t sj, int cs)
+{
+    for (int c = threadIdx.x; c < cs; c += blockDim.x) {
+        // cross-section position c -> local entry t0 (loc_j = 0), from the
+        // plan's table; its global offset and, in a ragged tile, whether it
+        // lies inside the tile, from the per-entry tables
+        const int t0 = cj[c];
+        if (ts.ragged && !entry_ok<MC>(code[t0], sd, ts)) continue;
+        const V *src = X + ts.base + goff[t0] - (int64_t)o * sj;
+        double2 acc[BJ];
+#pragma unroll
+        for (int r = 0; r < BJ; ++r) acc[r] = make_double2(0.0, 0.0);
+        for (int kb = k0; kb < k1; kb += NP) {
+            double2 y[NP];
+#pragma unroll
+            for (int u = 0; u < NP; ++u)
+                y[u] = kb + u < k1 ? to_d2<V>(src[(int64_t)(kb + u) * sj]) : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int u = 0; u < NP; ++u) {
+                const int k = kb + u;
+                if (k >= k1) break;  // uniform
+#pragma unroll
+                for (int r = 0; r < BJ; ++r) {
+                    if (r < e) {
+                        if (ADJ)
+                            acc[r] = cmac_conj(acc[r], Tj[k + (int64_t)d * (o + r)], y[u]);
+                        else
+                            acc[r] = cmac(acc[r], Tj[(o + r) + (int64_t)d * k], y[u]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < BJ; ++r)
+            if (r < e) tile[t0 + r * lsj] = csub(tile[t0 + r * lsj], acc[r]);
+    }
 }
 
 template <typename V, bool ADJ, int MC, bool PEN>
@@ -195,40 +243,19 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
         const int cs = sd.S / b;
         const double2 *Tj = Tbuf + sd.moff[j];
         const int *cj = cst + sd.csoff[j];
-        for (int c = threadIdx.x; c < cs; c += blockDim.x) {
-            // cross-section position c -> local entry t0 (loc_j = 0), from the
-            // plan's table; its global offset and, in a ragged tile, whether
-            // it lies inside the tile, from the per-entry tables
-            const int t0 = cj[c];
-            if (ts.ragged && !entry_ok<MC>(code[t0], sd, ts)) continue;
-            const int64_t g0 = ts.base + goff[t0];
-            double2 acc[kBmax];
-#pragma unroll
-            for (int r = 0; r < kBmax; ++r) acc[r] = make_double2(0.0, 0.0);
-            for (int kb = k0; kb < k1; kb += kPrefetch) {
-                double2 y[kPrefetch];
-#pragma unroll
-                for (int u = 0; u < kPrefetch; ++u)
-                    y[u] = kb + u < k1 ? to_d2<V>(X[g0 + (int64_t)(kb + u - o) * sj])
-                                       : make_double2(0.0, 0.0);
-#pragma unroll
-                for (int u = 0; u < kPrefetch; ++u) {
-                    const int k = kb + u;
-                    if (k >= k1) break;  // uniform
-#pragma unroll
-                    for (int r = 0; r < kBmax; ++r) {
-                        if (r < e) {
-                            if (ADJ)
-                                acc[r] = cmac_conj(acc[r], Tj[k + (int64_t)d * (o + r)], y[u]);
-                            else
-                                acc[r] = cmac(acc[r], Tj[(o + r) + (int64_t)d * k], y[u]);
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < kBmax; ++r)
-                if (r < e) tile[t0 + r * lsj] = csub(tile[t0 + r * lsj], acc[r]);
+        // the block size is a compile-time constant of the pull loop, so the
+        // row accumulators take only the registers the block needs and the
+        // rest go to loads in flight
+        switch (b) {
+#define SYLT_PULL(BJ, NP)                                                                         \
+    case BJ:                                                                                      \
+        pull_mode<V, ADJ, MC, BJ, NP>(X, Tj, cj, goff, code, sd, ts, tile, o, e, d, k0, k1, lsj, sj, \
+                                      cs);                                                        \
+        break;
+            SYLT_PULL(1, 16) SYLT_PULL(2, 16) SYLT_PULL(3, 16) SYLT_PULL(4, 12)
+            SYLT_PULL(5, 12) SYLT_PULL(6, 8) SYLT_PULL(7, 8) SYLT_PULL(8, 8)
+#undef SYLT_PULL
+            default: break;
         }
         __syncthreads();
     }

@@ -285,6 +285,9 @@ def main():
                           reps_m, torch)
         err = float(((Xm - X64).abs().max() / X64.abs().max()).item())
         mixed = {"ms": round(t_m, 3), "iterations": info["iterations"],
+                 "phase_ms": {"transforms": round(info["ms_transform"], 3),
+                              "sweeps": round(info["ms_sweep"], 3),
+                              "residuals": round(info["ms_residual"], 3)},
                  "rel_residual": info["rel_residual"],
                  "speedup_vs_fp64": round((t_fwd + t_sw + t_bwd) / t_m, 4),
                  "max_rel_diff_vs_fp64": err, "entries_per_s": ntot / (t_m * 1e-3)}

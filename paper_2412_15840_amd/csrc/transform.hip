@@ -741,7 +741,7 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
     double *part_b, double *part_r)
 {
     using MT = MfmaT<double>;
-    constexpr int RB = (2 * NN + 15) / 16;
+    constexpr int RB = (NN + 7) / 8;        // 16-row blocks (8 complex outputs each)
     constexpr int KS = (2 * NN + 3) / 4;
     constexpr int WAVES = kMfmaThreads / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -754,12 +754,12 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
         const int l = idx & 63;
         const int frag = idx >> 6;
         const int kk = frag % KS, rb = (frag / KS) % RB, q = frag / (KS * RB);
-        const int row = 16 * rb + (l & 15), k = 4 * kk + (l >> 4);
-        const int i = row >> 1, m = k >> 1;
+        const int r = l & 15, k = 4 * kk + (l >> 4);
+        const int i = 8 * rb + MT::out_of_row(r), m = k >> 1;
         double v = 0.0;
         if (i < NN && m < NN) {
             const double2 c = Abuf[pa.moff[q] + i + NN * m];
-            const int a = row & 1, b = k & 1;
+            const int a = MT::part_of_row(r), b = k & 1;
             v = a == b ? c.x : (a ? c.y : -c.y);
         }
         afr[idx] = v;
@@ -767,27 +767,38 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
     int *fbt = reinterpret_cast<int *>(afr + pa.ng * RB * KS * 64);
     build_fibre_table(fbt, pa, NN);
     const int nfull = pa.lb * (int)(pa.G / NN) * pa.rb;
+    // a zero operand after the table for lanes outside the tile
+    double *zslot = reinterpret_cast<double *>(fbt + ((pa.ng * nfull + 3) & ~3));
+    if (threadIdx.x == 0) zslot[0] = 0.0;
+    const int zidx = (int)(zslot - reinterpret_cast<double *>(xt));
     double2 shift = make_double2(0.0, 0.0);
     if (first)
         for (int i = 0; i < sing.count; ++i) shift = cadd(shift, Abuf[sing.off[i]]);
     // persistent: tiles blockIdx.x, blockIdx.x + gridDim.x, ...; the X entries
-    // of the next tile are loaded into registers while this one is multiplied
+    // and the combine source (B in the first pass, R after) of the next tile
+    // are loaded into registers while this one is multiplied
     const int64_t ntiles = pa.ntl * pa.ntr;
     int64_t t = blockIdx.x;
     if (t >= ntiles) return;
-    // X and the combine source (B in the first pass, R after) of the next
-    // tile are both prefetched into registers
     const double2 *src = first ? B : R;
     double pre_re[kResidualRegs], pre_im[kResidualRegs], src_re[kResidualRegs], src_im[kResidualRegs];
+    auto gaddr = [&](const TileCoord &c, int e, bool &ok) -> int64_t {
+        const int l = e & (pa.lb - 1);
+        const int rest = e >> pa.lbshift;
+        int g = rest, r = 0;
+        if (pa.rb > 1) {
+            g = rest % (int)pa.G;
+            r = rest / (int)pa.G;
+        }
+        ok = e < total && l < c.lbe && r < c.rbe;
+        return c.l0 + l + pa.Lin * (g + pa.G * (c.r0 + r));
+    };
     auto load_regs = [&](const TileCoord &c) {
 #pragma unroll
         for (int i = 0; i < kResidualRegs; ++i) {
-            const int e = threadIdx.x + i * kMfmaThreads;
-            const int l = e & (pa.lb - 1);
-            const int rest = e >> pa.lbshift;
-            const int g = rest % (int)pa.G, r = rest / (int)pa.G;
-            if (e < total && l < c.lbe && r < c.rbe) {
-                const int64_t gi = c.l0 + l + pa.Lin * (g + pa.G * (c.r0 + r));
+            bool ok;
+            const int64_t gi = gaddr(c, threadIdx.x + i * kMfmaThreads, ok);
+            if (ok) {
                 const double2 v = X[gi], w = src[gi];
                 pre_re[i] = v.x;
                 pre_im[i] = v.y;
@@ -798,6 +809,10 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
     };
     TileCoord tc = tile_coord_of(pa, t);
     load_regs(tc);
+    // the prefetch registers are complete on every path into the loop (here
+    // and before the last mode), so refilling the tile never waits on the
+    // R stores of the previous tile
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
     while (true) {
         double cur_re[kResidualRegs], cur_im[kResidualRegs];
 #pragma unroll
@@ -816,8 +831,8 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
         const TileCoord tcn = tile_coord_of(pa, tn < ntiles ? tn : t);
         if (tn < ntiles) load_regs(tcn);
         const double *tr = reinterpret_cast<const double *>(xt);
-        double *ar = reinterpret_cast<double *>(acc);
-        for (int q = 0; q < pa.ng; ++q) {
+        // one mode: acc += A_q x_q (tile), fibre groups of 16 on the matrix cores
+        auto mode = [&](int q) __attribute__((always_inline)) {
             const double *aq = afr + q * RB * KS * 64 + lane;
             const int nfib = pa.lb * (int)(pa.G / NN) * tc.rbe;
             const int stride = pa.lb * pa.gs[q];
@@ -825,44 +840,59 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
             const int *fq = fbt + q * nfull;
             for (int grp = wave; grp < ngroups; grp += WAVES) {
                 const int f = 16 * grp + (lane & 15);
-                const int base = (f < nfib && (f & (pa.lb - 1)) < tc.lbe) ? fq[f] : -1;
+                const int base = (f < nfib && (f & (pa.lb - 1)) < tc.lbe) ? fq[min(f, nfull - 1)] : -1;
                 const int kb = lane >> 4;
+                double bv[KS];
+#pragma unroll
+                for (int kk = 0; kk < KS; ++kk) {
+                    const int k = 4 * kk + kb;
+                    const int m = k >> 1;
+                    const int idx = (base >= 0 && m < NN) ? 2 * (base + m * stride) + (k & 1) : zidx;
+                    bv[kk] = tr[idx];
+                }
                 typename MT::acc d[RB];
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) d[rb] = typename MT::acc{0, 0, 0, 0};
 #pragma unroll
                 for (int kk = 0; kk < KS; ++kk) {
-                    const int k = 4 * kk + kb;
-                    const int m = k >> 1;
-                    const double b = (base >= 0 && m < NN) ? tr[2 * (base + m * stride) + (k & 1)] : 0.0;
 #pragma unroll
-                    for (int rb = 0; rb < RB; ++rb) d[rb] = MT::mma(aq[(rb * KS + kk) * 64], b, d[rb]);
+                    for (int rb = 0; rb < RB; ++rb) d[rb] = MT::mma(aq[(rb * KS + kk) * 64], bv[kk], d[rb]);
                 }
+                __builtin_amdgcn_sched_barrier(0);
                 if (base >= 0) {
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int row = 16 * rb + MT::row(lane, v);
-                            const int i = row >> 1;
-                            if (i < NN) ar[2 * (base + i * stride) + (row & 1)] += d[rb][v];
+                        for (int c = 0; c < 2; ++c) {
+                            const int i = 8 * rb + MT::out_of_row(MT::row(lane, 2 * c));
+                            if (i < NN) {
+                                const int e = base + i * stride;
+                                double2 a = acc[e];
+                                a.x += d[rb][2 * c];
+                                a.y += d[rb][2 * c + 1];
+                                acc[e] = a;
+                            }
                         }
                     }
                 }
             }
+        };
+        for (int q = 0; q + 1 < pa.ng; ++q) {
+            mode(q);
             __syncthreads();
         }
+        __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): the next tile is in registers
+        mode(pa.ng - 1);
+        __syncthreads();
         // R = src - acc, with this tile's source values kept in registers
         // (cur_*) while the next tile's were prefetched
         double sb = 0.0, sr = 0.0;
 #pragma unroll
         for (int i = 0; i < kResidualRegs; ++i) {
             const int e = threadIdx.x + i * kMfmaThreads;
-            const int l = e & (pa.lb - 1);
-            const int rest = e >> pa.lbshift;
-            const int g = rest % (int)pa.G, r = rest / (int)pa.G;
-            if (e < total && l < tc.lbe && r < tc.rbe) {
-                const int64_t gi = tc.l0 + l + pa.Lin * (g + pa.G * (tc.r0 + r));
+            bool ok;
+            const int64_t gi = gaddr(tc, e, ok);
+            if (ok) {
                 const double2 sv = make_double2(cur_re[i], cur_im[i]);
                 const double2 a = acc[e];
                 const double2 v = make_double2(sv.x - a.x, sv.y - a.y);
@@ -1033,8 +1063,8 @@ hipError_t launch_transform_from(const sylt_plan_s &p, int dir, const double2 *s
 size_t residual_mfma_lds(const PassDesc &pa)
 {
     const int n = pa.uniform_n;
-    const size_t frags = (size_t)pa.ng * ((2 * n + 15) / 16) * ((2 * n + 3) / 4) * 64;
-    return pa.lds_bytes(sizeof(double2)) * 2 + frags * sizeof(double) + fibre_table_bytes(pa, n);
+    const size_t frags = (size_t)pa.ng * ((n + 7) / 8) * ((2 * n + 3) / 4) * 64;
+    return pa.lds_bytes(sizeof(double2)) * 2 + frags * sizeof(double) + fibre_table_bytes(pa, n) + 32;
 }
 
 hipError_t launch_transform_with(const sylt_plan_s &p, const double2 *M, double2 *X, hipStream_t s)

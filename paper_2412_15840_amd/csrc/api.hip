@@ -541,9 +541,10 @@ int init_plan(sylt_plan_s *p, int N, const int64_t *n)
     return plan_sweep(*p);
 }
 
-// Remark 1: if every T_k is diagonal to rounding (each strictly upper entry
-// at most 64 n_k eps max|T_k|, as for normal A_k), the sweep becomes the
-// Hadamard product with the inverse eigenvalue sums; build its two tables.
+// Remark 1: if every T_k is diagonal to rounding (the Frobenius norm of its
+// strictly upper part at most 16 n_k eps ||T_k||_F, as for normal A_k), the
+// sweep becomes the Hadamard product with the inverse eigenvalue sums; build
+// its two tables.
 int plan_diagonal(sylt_plan_s *p, hipStream_t s)
 {
     p->diagT = false;
@@ -554,14 +555,18 @@ int plan_diagonal(sylt_plan_s *p, hipStream_t s)
     for (int j = 0; j < p->M; ++j) {
         const int n = p->cdim[j];
         const double2 *Tj = T.data() + p->moff[p->cmode[j]];
-        double big = 0.0, off = 0.0;
+        // the strictly upper part, as a whole (Frobenius norm), must be at the
+        // level of the rounding of a backward-stable Schur factor: dropping it
+        // is then a perturbation of T_k of the same order as that rounding
+        double all2 = 0.0, off2 = 0.0;
         for (int c = 0; c < n; ++c)
             for (int r = 0; r <= c; ++r) {
-                const double a = std::hypot(Tj[r + (int64_t)n * c].x, Tj[r + (int64_t)n * c].y);
-                big = std::max(big, a);
-                if (r < c) off = std::max(off, a);
+                const double2 v = Tj[r + (int64_t)n * c];
+                const double a2 = v.x * v.x + v.y * v.y;
+                all2 += a2;
+                if (r < c) off2 += a2;
             }
-        if (off > 64.0 * n * DBL_EPSILON * big) return SYLT_OK;
+        if (std::sqrt(off2) > 16.0 * n * DBL_EPSILON * std::sqrt(all2)) return SYLT_OK;
     }
     // low table: the longest prefix of compressed modes with at most 2^16 entries
     int split = 0;
@@ -643,6 +648,14 @@ class PhaseTimer {
     int n_ = 0, used_ = 0;
     bool ok_ = true;
 };
+
+// 2^-e for v in [2^e, 2^(e+1)), e clamped to [-1000, 1000]; 1 for v zero or
+// not finite.  A power of two: applying it and its inverse rounds nothing.
+double pow2_inverse(double v)
+{
+    if (!(v > 0.0) || !std::isfinite(v)) return 1.0;
+    return std::ldexp(1.0, -std::max(-1000, std::min(1000, std::ilogb(v))));
+}
 
 int64_t mixed_workspace(const sylt_plan_s *p)
 {
@@ -911,7 +924,19 @@ int sylt_solve(sylt_plan p, const sylt_opts *o, const double *B, double *X, void
     }
     float2 *R32 = reinterpret_cast<float2 *>(w);
     double *d_norms = p->dScratch + (p->scratch_bytes / sizeof(double) - 4);
-    SYLT_TRY(launch_convert_c128_c64(R32, Bc, p->ntot, s));
+    // Every right-hand side enters FP32 times a power of two that brings it
+    // near unit size (the first from max |B|, each residual from the size of
+    // the right-hand side before it, which the refinement contracts by about
+    // the FP32 accuracy), so neither B's own scale nor the shrinking residuals
+    // reach FP32's overflow or subnormal range; the correction is unscaled
+    // exactly in FP64.
+    double bmax = 0.0;
+    SYLT_TRY(launch_max_abs_c128(Bc, p->ntot, p->dScratch, d_norms + 2, s));
+    SYLT_TRY(hipMemcpyAsync(&bmax, d_norms + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+    SYLT_TRY(hipStreamSynchronize(s));
+    double sc_in = pow2_inverse(bmax);  // scale of the right-hand side now in R32
+    double sc_next = sc_in;              // scale of the next residual written to R32
+    SYLT_TRY(launch_convert_c128_c64(R32, Bc, p->ntot, sc_in, s));
     int it = 0;
     double rel = -1.0;
     int st = SYLT_E_NO_CONVERGENCE;
@@ -925,14 +950,16 @@ int sylt_solve(sylt_plan p, const sylt_opts *o, const double *B, double *X, void
         tm.mark();
         SYLT_TRY(launch_transform(*p, SYLT_FROM_SCHUR, SYLT_MIXED, R32, s));
         tm.mark();
-        SYLT_TRY(launch_axpy_c64(Xc, R32, p->ntot, it == 0, s));
+        SYLT_TRY(launch_axpy_c64(Xc, R32, p->ntot, it == 0, 1.0 / sc_in, s));
         ++it;
         tm.mark();
-        SYLT_TRY(launch_residual(*p, Bc, Xc, R64, R32, d_norms, s));
+        SYLT_TRY(launch_residual(*p, Bc, Xc, R64, R32, d_norms, s, sc_next));
         tm.mark();
         double nrm[2];
         SYLT_TRY(hipMemcpyAsync(nrm, d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         SYLT_TRY(hipStreamSynchronize(s));
+        sc_in = sc_next;
+        sc_next = pow2_inverse(std::sqrt(nrm[0] / (double)p->ntot));
         ms_tr += tm.span(0) + tm.span(2);
         ms_sw += tm.span(1);
         ms_res += tm.span(4);

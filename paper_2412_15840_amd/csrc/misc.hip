@@ -114,28 +114,76 @@ __global__ void min_sqrt_kernel(const double *__restrict__ partial, int n, doubl
 }
 
 // ------------------------------------------------------------ elementwise
-__global__ void convert_kernel(float2 *__restrict__ out, const double2 *__restrict__ in, int64_t n)
+// out = complex64(scale * in); scale is a power of two, so only the cast rounds
+__global__ void convert_kernel(float2 *__restrict__ out, const double2 *__restrict__ in, int64_t n,
+                               double scale)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double2 v = in[i];
-        out[i] = make_float2((float)v.x, (float)v.y);
+        out[i] = make_float2((float)(v.x * scale), (float)(v.y * scale));
     }
 }
 
-// X += D (assign == 0) or X = D (assign != 0), D complex64, X complex128
+// X += unscale D (assign == 0) or X = unscale D (assign != 0), D complex64,
+// X complex128; unscale is a power of two (exact)
 __global__ void axpy_kernel(double2 *__restrict__ X, const float2 *__restrict__ D, int64_t n,
-                            int assign)
+                            int assign, double unscale)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const float2 d = D[i];
+        const double dx = (double)d.x * unscale, dy = (double)d.y * unscale;
         if (assign) {
-            X[i] = make_double2(d.x, d.y);
+            X[i] = make_double2(dx, dy);
         } else {
             const double2 x = X[i];
-            X[i] = make_double2(x.x + (double)d.x, x.y + (double)d.y);
+            X[i] = make_double2(x.x + dx, x.y + dy);
         }
+    }
+}
+
+// per-block maxima of max(|re|, |im|) (a NaN anywhere makes its block's NaN)
+__global__ void max_abs_kernel(const double2 *__restrict__ in, int64_t n, double *partial)
+{
+    __shared__ double red[kThreads / 64];
+    double m = 0.0;
+    bool nan = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 v = in[i];
+        nan |= v.x != v.x || v.y != v.y;
+        m = fmax(m, fmax(fabs(v.x), fabs(v.y)));
+    }
+    if (nan) m = NAN;
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_down(m, off, 64);
+        m = (m != m || o != o) ? NAN : fmax(m, o);
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = red[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) t = (t != t || red[w] != red[w]) ? NAN : fmax(t, red[w]);
+        partial[blockIdx.x] = t;
+    }
+}
+
+__global__ void max_reduce_kernel(const double *__restrict__ partial, int n, double *out)
+{
+    __shared__ double red[kThreads / 64];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) m = (m != m || partial[i] != partial[i]) ? NAN : fmax(m, partial[i]);
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_down(m, off, 64);
+        m = (m != m || o != o) ? NAN : fmax(m, o);
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = red[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) t = (t != t || red[w] != red[w]) ? NAN : fmax(t, red[w]);
+        *out = t;
     }
 }
 
@@ -246,15 +294,28 @@ hipError_t launch_separation(const sylt_plan_s &p, double *d_out, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_convert_c128_c64(float2 *out, const double2 *in, int64_t n, hipStream_t s)
+hipError_t launch_convert_c128_c64(float2 *out, const double2 *in, int64_t n, double scale,
+                                   hipStream_t s)
 {
-    hipLaunchKernelGGL(convert_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, out, in, n);
+    hipLaunchKernelGGL(convert_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, out, in, n, scale);
     return hipGetLastError();
 }
 
-hipError_t launch_axpy_c64(double2 *X, const float2 *D, int64_t n, int assign, hipStream_t s)
+hipError_t launch_axpy_c64(double2 *X, const float2 *D, int64_t n, int assign, double unscale,
+                           hipStream_t s)
 {
-    hipLaunchKernelGGL(axpy_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, X, D, n, assign);
+    hipLaunchKernelGGL(axpy_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, X, D, n, assign,
+                       unscale);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_abs_c128(const double2 *in, int64_t n, double *partial, double *d_out,
+                               hipStream_t s)
+{
+    const int blocks = (int)std::max<int64_t>(
+        1, std::min<int64_t>((n + kThreads - 1) / kThreads, kMaxAbsBlocks));
+    hipLaunchKernelGGL(max_abs_kernel, dim3(blocks), dim3(kThreads), 0, s, in, n, partial);
+    hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(kThreads), 0, s, partial, blocks, d_out);
     return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@ constexpr int kSweepPencilMax = 20;   // longest mode-0 pencil held in one lane'
 constexpr int kSweepPencilModes = 8;  // most tiled modes of the pencil form
 constexpr int kResidualMfmaCap = 4096;  // tile entries of the matrix-core residual pass
 constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;  // fixed device scratch per device
+constexpr int kMaxAbsBlocks = 4096;  // partial maxima of the max-abs reduction
 
 // ----------------------------------------------------------------- complex
 // double2 / float2 hold (re, im).  All products are written as explicit fused
@@ -250,10 +251,10 @@ hipError_t launch_sweep(const sylt_plan_s &p, int op, int precision, void *X, hi
 // the two partial-sum tables of the diagonal sweep (p.dslo, p.dshi)
 hipError_t launch_diag_tables(const sylt_plan_s &p, hipStream_t s);
 // R64 (complex128, may alias B) = B - sum_k A_k x_k X; if R32 != nullptr the
-// final pass also stores R as complex64.  Partial sums of |R|^2 and |B|^2 are
-// reduced into norms2_dev[0..1] (device).
+// final pass also stores r32_scale R (a power of two) as complex64.  Partial
+// sums of |R|^2 and |B|^2 (unscaled) are reduced into norms2_dev[0..1] (device).
 hipError_t launch_residual(const sylt_plan_s &p, const double2 *B, const double2 *X, double2 *R64,
-                           float2 *R32, double *norms2_dev, hipStream_t s);
+                           float2 *R32, double *norms2_dev, hipStream_t s, double r32_scale = 1.0);
 // the same with the matrices M_k of Mbuf (offsets p.moff) in place of A_k
 // passes of the residual as launched (matrix-core or VALU list)
 inline size_t residual_pass_count(const sylt_plan_s &p)
@@ -264,7 +265,7 @@ inline size_t residual_pass_count(const sylt_plan_s &p)
 size_t residual_mfma_lds(const PassDesc &pa);
 hipError_t launch_residual_with(const sylt_plan_s &p, const double2 *Mbuf, const double2 *B,
                                 const double2 *X, double2 *R64, float2 *R32, double *norms2_dev,
-                                hipStream_t s);
+                                hipStream_t s, double r32_scale = 1.0);
 // chain of mode products with the matrices of M (offsets p.moff; singleton modes skipped)
 hipError_t launch_transform_with(const sylt_plan_s &p, const double2 *M, double2 *X, hipStream_t s);
 // E_k = exp(t T_k) for every mode into p.dE, and p.dEvo = {prod of the
@@ -273,8 +274,15 @@ hipError_t launch_expm(const sylt_plan_s &p, double t, hipStream_t s);
 // out = c[0] x + c[1] y with device scalars c (out may alias x or y)
 hipError_t launch_lincomb(double2 *out, const double2 *x, const double2 *y, const double2 *c,
                           int64_t n, hipStream_t s);
-hipError_t launch_axpy_c64(double2 *X, const float2 *D, int64_t n, int assign, hipStream_t s);
-hipError_t launch_convert_c128_c64(float2 *out, const double2 *in, int64_t n, hipStream_t s);
+// X (+)= unscale D and out = complex64(scale in), unscale and scale powers of two
+hipError_t launch_axpy_c64(double2 *X, const float2 *D, int64_t n, int assign, double unscale,
+                           hipStream_t s);
+hipError_t launch_convert_c128_c64(float2 *out, const double2 *in, int64_t n, double scale,
+                                   hipStream_t s);
+// *d_out = max over entries of max(|re|, |im|) (NaN if any entry is NaN);
+// partial holds kMaxAbsBlocks doubles
+hipError_t launch_max_abs_c128(const double2 *in, int64_t n, double *partial, double *d_out,
+                               hipStream_t s);
 hipError_t launch_copy_c128(double2 *out, const double2 *in, int64_t n, hipStream_t s);
 hipError_t launch_grad_A(const sylt_plan_s &p, const double2 *G, const double2 *X, double2 *const *GA,
                          void *ws, size_t ws_bytes, hipStream_t s);

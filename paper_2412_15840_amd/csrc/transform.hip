@@ -625,13 +625,13 @@ __device__ __forceinline__ void residual_reduce(double sb, double sr, int first,
                                                 unsigned char *smem_raw);
 
 // R = src - acc on the tile (src = B in the first pass, R after), written as
-// complex128 (and complex64 in the last pass if R32); per-tile partial sums of
-// |B|^2 (first pass) and |R|^2 (last pass) in a fixed order.
+// complex128 (and as complex64 r32_scale R in the last pass if R32); per-tile
+// partial sums of |B|^2 (first pass) and |R|^2 (last pass) in a fixed order.
 __device__ __forceinline__ void residual_finish(const double2 *__restrict__ B, double2 *R, float2 *R32,
                                                 const double2 *acc, const PassDesc &pa,
                                                 const TileCoord &tc, int first, int last,
                                                 double *part_b, double *part_r, int64_t tile,
-                                                unsigned char *smem_raw)
+                                                unsigned char *smem_raw, double r32_scale)
 {
     // combine with the source and write; accumulate the norms
     double sb = 0.0, sr = 0.0;
@@ -650,7 +650,7 @@ __device__ __forceinline__ void residual_finish(const double2 *__restrict__ B, d
             if (first) sb += s.x * s.x + s.y * s.y;
             if (last) {
                 sr += v.x * v.x + v.y * v.y;
-                if (R32) R32[gi] = make_float2((float)v.x, (float)v.y);
+                if (R32) R32[gi] = make_float2((float)(v.x * r32_scale), (float)(v.y * r32_scale));
             }
             if (!last || !R32) R[gi] = v;
         }
@@ -691,7 +691,7 @@ template <int NN>
 __global__ void __launch_bounds__(kThreads) residual_pass_kernel(
     const double2 *__restrict__ B, const double2 *__restrict__ X, double2 *R, float2 *R32,
     const double2 *__restrict__ Abuf, PassDesc pa, SingletonList sing, int first, int last,
-    double *part_b, double *part_r)
+    double *part_b, double *part_r, double r32_scale)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double2 *xt = reinterpret_cast<double2 *>(smem_raw);
@@ -725,7 +725,8 @@ __global__ void __launch_bounds__(kThreads) residual_pass_kernel(
         }
         __syncthreads();
     }
-    residual_finish(B, R, R32, acc, pa, tc, first, last, part_b, part_r, blockIdx.x, smem_raw);
+    residual_finish(B, R, R32, acc, pa, tc, first, last, part_b, part_r, blockIdx.x, smem_raw,
+                    r32_scale);
 }
 
 constexpr int kResidualRegs = kResidualMfmaCap / kMfmaThreads;  // X entries per lane of a tile
@@ -738,7 +739,7 @@ template <int NN>
 __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
     const double2 *__restrict__ B, const double2 *__restrict__ X, double2 *R, float2 *R32,
     const double2 *__restrict__ Abuf, PassDesc pa, SingletonList sing, int first, int last,
-    double *part_b, double *part_r)
+    double *part_b, double *part_r, double r32_scale)
 {
     using MT = MfmaT<double>;
     constexpr int RB = (NN + 7) / 8;        // 16-row blocks (8 complex outputs each)
@@ -899,7 +900,7 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
                 if (first) sb += sv.x * sv.x + sv.y * sv.y;
                 if (last) {
                     sr += v.x * v.x + v.y * v.y;
-                    if (R32) R32[gi] = make_float2((float)v.x, (float)v.y);
+                    if (R32) R32[gi] = make_float2((float)(v.x * r32_scale), (float)(v.y * r32_scale));
                 }
                 if (!last || !R32) R[gi] = v;
             }
@@ -1077,14 +1078,14 @@ hipError_t launch_transform_with(const sylt_plan_s &p, const double2 *M, double2
 }
 
 hipError_t launch_residual(const sylt_plan_s &p, const double2 *B, const double2 *X, double2 *R64,
-                           float2 *R32, double *norms2_dev, hipStream_t s)
+                           float2 *R32, double *norms2_dev, hipStream_t s, double r32_scale)
 {
-    return launch_residual_with(p, p.dA, B, X, R64, R32, norms2_dev, s);
+    return launch_residual_with(p, p.dA, B, X, R64, R32, norms2_dev, s, r32_scale);
 }
 
 hipError_t launch_residual_with(const sylt_plan_s &p, const double2 *Mbuf, const double2 *B,
                                 const double2 *X, double2 *R64, float2 *R32, double *norms2_dev,
-                                hipStream_t s)
+                                hipStream_t s, double r32_scale)
 {
     const std::vector<PassDesc> &passes = p.residual_mfma ? p.mrpasses : p.rpasses;
     const int P = (int)passes.size();
@@ -1117,7 +1118,7 @@ hipError_t launch_residual_with(const sylt_plan_s &p, const double2 *Mbuf, const
         const int64_t grid = std::min<int64_t>(tiles, (int64_t)device_cus() * occ);              \
         hipLaunchKernelGGL(residual_mfma_kernel<NNV>, dim3((unsigned)grid), dim3(kMfmaThreads),   \
                            mlds, s, B, X, R64, last ? R32 : nullptr, Mbuf, pa, sing, first, last, \
-                           part_b, part_r);                                                       \
+                           part_b, part_r, r32_scale);                                            \
     } while (0)
             switch (pa.uniform_n) {
                 case 8: SYLT_MRLAUNCH(8); break;
@@ -1141,7 +1142,8 @@ hipError_t launch_residual_with(const sylt_plan_s &p, const double2 *Mbuf, const
         e = allow_lds(KER, lds);                                                                \
         if (e != hipSuccess) return e;                                                          \
         hipLaunchKernelGGL(KER, dim3((unsigned)tiles), dim3(kThreads), lds, s, B, X, R64,       \
-                           last ? R32 : nullptr, Mbuf, pa, sing, first, last, part_b, part_r);  \
+                           last ? R32 : nullptr, Mbuf, pa, sing, first, last, part_b, part_r,   \
+                           r32_scale);                                                          \
     } while (0)
         switch (pa.uniform_n) {
             case 2: SYLT_RLAUNCH(residual_pass_kernel<2>); break;

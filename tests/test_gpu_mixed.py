@@ -49,6 +49,32 @@ def test_mixed_refinement_reaches_1e12(name, n, seed):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("scale", [1e-42, 1e-30, 1e30, 1e36])
+def test_mixed_refinement_far_from_unit_scale(scale):
+    """B scaled far from unit size: 1e-42 lies below FP32's normal range and
+    1e36 near its top, so a plain FP32 copy of B (or of the shrinking
+    residuals) would flush or overflow.  The solve scales each right-hand side
+    by a power of two before the FP32 cast; it must still reach 1e-12 and the
+    FP64 oracle's solution of the same scaled problem."""
+    sylt = _sylt()
+    n, seed = (16, 16, 16), 83
+    banner(f"mixed scale {scale:g} {n}")
+    A = wl.coefficient_matrices(n, seed)
+    B = wl.complex_normal(int(np.prod(n)), seed) * scale
+    plan = sylt.Plan.factor(n, [torch.from_numpy(a) for a in A])
+    X, info = sylt.solve(plan, dev(B), precision="mixed", rtol=1e-12, max_iter=8, info=True)
+    torch.cuda.synchronize()
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-12
+    Xh = host(X)
+    assert np.all(np.isfinite(Xh))
+    res = oracle.relative_residual(n, A, Xh, B)
+    err = relmax(Xh, oracle.solve(n, A, B))
+    print(f"[mixed] scale {scale:g}: iterations {info['iterations']}, residual (oracle) {res:.3e}, "
+          f"error vs FP64 oracle {err:.3e}", flush=True)
+    assert res <= 1e-12
+    assert err <= 1e-10
+
+
 def test_mixed_reports_no_convergence():
     sylt = _sylt()
     rng = np.random.default_rng(72)

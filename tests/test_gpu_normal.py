@@ -114,3 +114,28 @@ def test_evolution_with_normal_matrices():
     assert plan.describe()["sweep"]["diagonal"] is True
     X = host(sylt.evolve(plan, 0.2, dev(b), dev(x0)))
     assert relmax(X, oracle.evolve(n, A, b, x0, 0.2)) <= 1e-11
+
+
+@pytest.mark.parametrize("scale,fast", [(0.25, True), (64.0, False)])
+def test_nearly_normal_threshold(scale, fast):
+    """A_k = Q (D + E) Q^* with E strictly upper triangular of Frobenius norm
+    `scale` times the planner's threshold 16 n eps ||T||_F: under it the
+    Hadamard sweep is taken (the dropped part is a perturbation of rounding
+    size), over it the tiled sweep; both solves meet the 1e-12 gate."""
+    sylt = _sylt()
+    rng = np.random.default_rng(11)
+    n = (12, 9, 7)
+    A = []
+    for k in n:
+        Z = rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k))
+        Q, _ = np.linalg.qr(Z)
+        D = np.diag(3.0 + rng.standard_normal(k) + 1j * rng.standard_normal(k))
+        E = np.triu(rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k)), 1)
+        target = scale * 16 * k * np.finfo(float).eps * np.linalg.norm(D)
+        E *= target / np.linalg.norm(E)
+        A.append(Q @ (D + E) @ Q.conj().T)
+    b = crandn(int(np.prod(n)), rng)
+    plan = sylt.Plan.factor(list(n), [dev(a) for a in A])
+    assert plan.describe()["sweep"]["diagonal"] is fast
+    X = host(sylt.solve(plan, dev(b)))
+    assert relmax(X, oracle.solve(n, A, b)) <= 1e-12

@@ -386,7 +386,11 @@ int plan_sweep(sylt_plan_s &p, const int *force_b)
     }
     // pencil form of the local solve: one mode-0 pencil (loc_0 = 0 .. b_0-1)
     // per lane, the waves grouped by the pencil's index sum over the other
-    // modes; it needs every group to fit the workgroup's waves
+    // modes; it needs every group to fit the workgroup's waves.  A tile whose
+    // last block along mode j >= 1 is short holds only the pencils with
+    // loc_j < e_j; each such shape (a mask over modes 1..M-1) gets its own
+    // packing, so a short tile's pencils fill fewer waves and the others skip
+    // the entry work.
     sd.penc = 0;
     sd.pen_long = 0;
     for (int j = 1; j < M; ++j) sd.pen_long |= b[j] > 3;
@@ -394,20 +398,35 @@ int plan_sweep(sylt_plan_s &p, const int *force_b)
         bitpos <= 17) {
         const int b0 = b[0];
         const int np = (int)(S / b0);
-        std::vector<std::vector<int>> grp(nll - (b0 - 1));
-        for (int pcl = 0; pcl < np; ++pcl) {
-            const int64_t t0 = (int64_t)pcl * b0;
-            grp[lev[t0]].push_back((int)t0 | (int)(code[t0] << 14));
-        }
-        int waves = 0;
-        for (const auto &g : grp) waves += (int)((g.size() + 63) / 64);
-        if (waves <= kSweepThreads / 64) {
-            std::vector<int> tab(kSweepThreads, -1);
+        const int nshape = 1 << (M - 1);
+        std::vector<int> tab((size_t)nshape * kSweepThreads, -1);
+        bool fits = true;
+        for (int shape = 0; shape < nshape && fits; ++shape) {
+            int e[kMaxModes];
+            for (int j = 1; j < M; ++j)
+                e[j] = (shape >> (j - 1)) & 1 ? p.cdim[j] - (sd.nb[j] - 1) * b[j] : b[j];
+            std::vector<std::vector<int>> grp(nll - (b0 - 1));
+            for (int pcl = 0; pcl < np; ++pcl) {
+                const int64_t t0 = (int64_t)pcl * b0;
+                bool in = true;
+                for (int j = 1; j < M; ++j)
+                    in = in && (int)((code[t0] >> sd.bitoff[j]) & ((1ull << sd.bitw[j]) - 1ull)) < e[j];
+                if (in) grp[lev[t0]].push_back((int)t0 | (int)(code[t0] << 14));
+            }
+            int waves = 0;
+            for (const auto &g : grp) waves += (int)((g.size() + 63) / 64);
+            if (waves > kSweepThreads / 64) {
+                fits = false;
+                break;
+            }
+            int *ts = tab.data() + (size_t)shape * kSweepThreads;
             int w = 0;
             for (const auto &g : grp)
                 for (size_t s0 = 0; s0 < g.size(); s0 += 64, ++w)
                     for (size_t i = s0; i < std::min(g.size(), s0 + 64); ++i)
-                        tab[(size_t)w * 64 + (i - s0)] = g[i];
+                        ts[(size_t)w * 64 + (i - s0)] = g[i];
+        }
+        if (fits) {
             lanetab.swap(tab);
             sd.penc = 1;
             sd.packed = 0;

@@ -76,6 +76,8 @@ struct TileState {
     int e[kMaxModes];
     int64_t base;
     int ragged;
+    int shape;  // modes 1..M-1 whose block is short in this tile (bit j-1)
+    int nll;    // local levels of this tile: 1 + sum_j (e_j - 1)
     double2 shift;
 };
 
@@ -165,7 +167,7 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
     if (threadIdx.x == 0) {
         int rem = tiles[tile_slot(blockIdx.x, gridDim.x)];
         int64_t base = 0;
-        int ragged = 0;
+        int ragged = 0, shape = 0, nll = 1;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             const int P = rem % sd.nb[j];
@@ -173,8 +175,12 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
             ts.o[j] = P * sd.b[j];
             ts.e[j] = min(sd.b[j], sd.d[j] - ts.o[j]);
             ragged |= ts.e[j] < sd.b[j];
+            if (j > 0) shape |= (ts.e[j] < sd.b[j]) << (j - 1);
+            nll += ts.e[j] - 1;
             base += (int64_t)ts.o[j] * sd.s[j];
         }
+        ts.shape = shape;
+        ts.nll = nll;
         double2 sh = make_double2(0.0, 0.0);
         for (int i = 0; i < sd.nsing; ++i) sh = cadd(sh, Tbuf[sd.singoff[i]]);
         ts.base = base;
@@ -195,7 +201,7 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
         }
     }
     // this lane's pencil (pencil form of the local solve)
-    const int pen_item = PEN ? lanetab[threadIdx.x] : -1;
+    const int pen_item = PEN ? lanetab[ts.shape * kThreads + threadIdx.x] : -1;
     // this lane's local-solve work, all levels at once (one memory latency)
     int pk[kMaxRounds];
     if (!PEN && sd.packed) {
@@ -386,7 +392,8 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
         // A wave is active at the e0 local levels g .. g + e0 - 1, one entry
         // each; before and after them it only takes part in the barriers, so
         // every wave passes the same nll barriers.
-        const int before = lead < 0 ? sd.nll : (ADJ ? g : sd.nll - g - e0);
+        const int nll = ts.nll;
+        const int before = lead < 0 ? nll : (ADJ ? g : nll - g - e0);
         for (int i = 0; i < before; ++i) __syncthreads();
         if (lead >= 0) {
             if (ADJ) {
@@ -405,7 +412,7 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
                     }
                 });
             }
-            const int after = ADJ ? sd.nll - g - e0 : g;
+            const int after = ADJ ? nll - g - e0 : g;
             for (int i = 0; i < after; ++i) __syncthreads();
         }
     } else if (sd.packed) {

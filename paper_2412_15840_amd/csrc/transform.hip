@@ -271,6 +271,26 @@ __device__ __forceinline__ TileCoord tile_coord_of(const PassDesc &pa, int64_t t
     return c;
 }
 
+// Tile walk of a persistent pass.  Workgroups are dealt to the XCDs
+// round-robin (workgroup b runs on XCD b % 8), and tiles t, t + 1 share the
+// cache lines at their common edge (runs of lb entries need not start on a
+// line).  XCD x therefore owns the contiguous range [x T / 8, (x + 1) T / 8),
+// which its workgroups walk together, so neighbouring tiles run at the same
+// time behind the same L2.  Grids that are not a multiple of 8 walk with
+// stride G.
+constexpr int kXcds = 8;
+struct TileWalk {
+    int64_t t, step, end;
+};
+__device__ __forceinline__ TileWalk tile_walk(int64_t ntiles)
+{
+    const int b = blockIdx.x, G = gridDim.x;
+    if (G % kXcds != 0) return TileWalk{b, G, ntiles};
+    const int x = b % kXcds;
+    const int64_t lo = ntiles * x / kXcds, hi = ntiles * (x + 1) / kXcds;
+    return TileWalk{lo + b / kXcds, G / kXcds, hi};
+}
+
 template <typename V, int NN, int P>
 __global__ void __launch_bounds__(kPipeThreads) transform_pipe_kernel(V *X, const V *Xs,
                                                                       const V *__restrict__ Mbuf,
@@ -287,8 +307,9 @@ __global__ void __launch_bounds__(kPipeThreads) transform_pipe_kernel(V *X, cons
 
     using R = typename CTraits<V>::R;
     R pre_re[kPipeRegs], pre_im[kPipeRegs];
-    int64_t t = blockIdx.x;
-    if (t >= ntiles) return;
+    const TileWalk walk = tile_walk(ntiles);
+    int64_t t = walk.t;
+    if (t >= walk.end) return;
     // this lane's tile entries e = lane + i*512 -> (l, g, r); their offsets
     // from the tile origin are the same for every tile of the pass
     int64_t off[kPipeRegs];
@@ -329,9 +350,9 @@ __global__ void __launch_bounds__(kPipeThreads) transform_pipe_kernel(V *X, cons
             }
         }
         __syncthreads();
-        const int64_t tn = t + gridDim.x;
-        const TileCoord tcn = tile_coord_of(pa, tn < ntiles ? tn : t);
-        if (tn < ntiles) load_regs(tcn);
+        const int64_t tn = t + walk.step;
+        const TileCoord tcn = tile_coord_of(pa, tn < walk.end ? tn : t);
+        if (tn < walk.end) load_regs(tcn);
         for (int q = 0; q < pa.ng; ++q) {
             const int nfib = pa.lb * (int)(pa.G / NN) * tc.rbe;
             const int stride = pa.lb * pa.gs[q];
@@ -370,7 +391,7 @@ __global__ void __launch_bounds__(kPipeThreads) transform_pipe_kernel(V *X, cons
                 if (ok) X[org + off[i]] = tile[threadIdx.x + i * kPipeThreads];
             }
         }
-        if (tn >= ntiles) break;
+        if (tn >= walk.end) break;
         __syncthreads();
         t = tn;
         tc = tcn;
@@ -460,8 +481,9 @@ __global__ void __launch_bounds__(kMfmaThreads) transform_mfma_kernel(V *X, cons
     const int zidx = (int)(zslot - reinterpret_cast<R *>(tile));
 
     R pre_re[kMfmaRegs], pre_im[kMfmaRegs];
-    int64_t t = blockIdx.x;
-    if (t >= ntiles) return;
+    const TileWalk walk = tile_walk(ntiles);
+    int64_t t = walk.t;
+    if (t >= walk.end) return;
     // global address of tile entry e (rb == 1 needs no division)
     auto gaddr = [&](const TileCoord &c, int e, bool &ok) -> int64_t {
         const int l = e & (pa.lb - 1);
@@ -502,9 +524,9 @@ __global__ void __launch_bounds__(kMfmaThreads) transform_mfma_kernel(V *X, cons
             }
         }
         __syncthreads();
-        const int64_t tn = t + gridDim.x;
-        const TileCoord tcn = tile_coord_of(pa, tn < ntiles ? tn : t);
-        if (tn < ntiles) load_regs(tcn);
+        const int64_t tn = t + walk.step;
+        const TileCoord tcn = tile_coord_of(pa, tn < walk.end ? tn : t);
+        if (tn < walk.end) load_regs(tcn);
         // one mode of the pass: the products of all fibres of mode q, written
         // back into LDS, or (the last mode) straight to memory
         auto mode = [&](int q, bool last) __attribute__((always_inline)) {
@@ -572,7 +594,7 @@ __global__ void __launch_bounds__(kMfmaThreads) transform_mfma_kernel(V *X, cons
         // not wait on those stores
         __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
         mode(pa.ng - 1, true);
-        if (tn >= ntiles) break;
+        if (tn >= walk.end) break;
         __syncthreads();  // every wave has read the tile before the refill
         t = tn;
         tc = tcn;
@@ -775,12 +797,13 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
     double2 shift = make_double2(0.0, 0.0);
     if (first)
         for (int i = 0; i < sing.count; ++i) shift = cadd(shift, Abuf[sing.off[i]]);
-    // persistent: tiles blockIdx.x, blockIdx.x + gridDim.x, ...; the X entries
-    // and the combine source (B in the first pass, R after) of the next tile
-    // are loaded into registers while this one is multiplied
+    // persistent (tile_walk); the X entries and the combine source (B in the
+    // first pass, R after) of the next tile are loaded into registers while
+    // this one is multiplied
     const int64_t ntiles = pa.ntl * pa.ntr;
-    int64_t t = blockIdx.x;
-    if (t >= ntiles) return;
+    const TileWalk walk = tile_walk(ntiles);
+    int64_t t = walk.t;
+    if (t >= walk.end) return;
     const double2 *src = first ? B : R;
     double pre_re[kResidualRegs], pre_im[kResidualRegs], src_re[kResidualRegs], src_im[kResidualRegs];
     auto gaddr = [&](const TileCoord &c, int e, bool &ok) -> int64_t {
@@ -828,9 +851,9 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
             }
         }
         __syncthreads();
-        const int64_t tn = t + gridDim.x;
-        const TileCoord tcn = tile_coord_of(pa, tn < ntiles ? tn : t);
-        if (tn < ntiles) load_regs(tcn);
+        const int64_t tn = t + walk.step;
+        const TileCoord tcn = tile_coord_of(pa, tn < walk.end ? tn : t);
+        if (tn < walk.end) load_regs(tcn);
         const double *tr = reinterpret_cast<const double *>(xt);
         // one mode: acc += A_q x_q (tile), fibre groups of 16 on the matrix cores
         auto mode = [&](int q) __attribute__((always_inline)) {
@@ -906,25 +929,37 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
             }
         }
         residual_reduce(sb, sr, first, last, part_b, part_r, t, smem_raw);
-        if (tn >= ntiles) break;
+        if (tn >= walk.end) break;
         __syncthreads();
         t = tn;
         tc = tcn;
     }
 }
 
-__global__ void reduce_sum_kernel(const double *__restrict__ in, int64_t n, double *out)
+// one workgroup of kReduceThreads lanes, fixed order: lane l sums entries
+// l + kReduceThreads (8 i + u) into accumulator u (eight loads in flight), the
+// accumulators, then the lanes of a wave and the waves are added in a fixed
+// order
+constexpr int kReduceThreads = 1024;
+__global__ void __launch_bounds__(kReduceThreads) reduce_sum_kernel(const double *__restrict__ in,
+                                                                    int64_t n, double *out)
 {
-    // one workgroup, fixed order
-    __shared__ double red[kThreads / 64];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += in[i];
+    __shared__ double red[kReduceThreads / 64];
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i0 = threadIdx.x; i0 < n; i0 += 8 * (int64_t)kReduceThreads) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t i = i0 + (int64_t)u * kReduceThreads;
+            a[u] += i < n ? in[i] : 0.0;
+        }
+    }
+    double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+        for (int w = 0; w < kReduceThreads / 64; ++w) t += red[w];
         *out = t;
     }
 }
@@ -1130,10 +1165,10 @@ hipError_t launch_residual_with(const sylt_plan_s &p, const double2 *Mbuf, const
             e = hipGetLastError();
             if (e != hipSuccess) return e;
             if (first && norms2_dev)
-                hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(kThreads), 0, s, part_b, tiles,
+                hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(kReduceThreads), 0, s, part_b, tiles,
                                    norms2_dev + 1);
             if (last && norms2_dev)
-                hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(kThreads), 0, s, part_r, tiles,
+                hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(kReduceThreads), 0, s, part_r, tiles,
                                    norms2_dev + 0);
             continue;
         }
@@ -1157,10 +1192,10 @@ hipError_t launch_residual_with(const sylt_plan_s &p, const double2 *Mbuf, const
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (first && norms2_dev)
-            hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(kThreads), 0, s, part_b, tiles,
+            hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(kReduceThreads), 0, s, part_b, tiles,
                                norms2_dev + 1);
         if (last && norms2_dev)
-            hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(kThreads), 0, s, part_r, tiles,
+            hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(kReduceThreads), 0, s, part_r, tiles,
                                norms2_dev + 0);
     }
     return hipGetLastError();

@@ -53,11 +53,12 @@ def source_digest(relpath):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` at `workload` from the committed
-    counter summary (profiles/kernel_traffic.txt: FETCH_SIZE and WRITE_SIZE,
-    each scaled by what the counter reads for a copy of known size).  None if
-    absent or if the kernel's source changed since the counters were taken."""
+def measured_counters(kernel, workload):
+    """Counter figures of `kernel` at `workload` from the committed summary
+    (profiles/kernel_traffic.txt): HBM bytes per launch (FETCH_SIZE and
+    WRITE_SIZE, each scaled by what the counter reads for a copy of known
+    size), the matrix-core busy fraction and the L2 hit rate.  None if absent
+    or if the kernel's source changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "kernel_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -69,7 +70,12 @@ def measured_traffic(kernel, workload):
             continue
         if f.get("source_sha256") != source_digest(f.get("source", "")):
             return None
-        return float(f["hbm_bytes_per_launch"])
+        out = {"traffic": float(f["hbm_bytes_per_launch"])}
+        if "mfma_busy" in f:
+            out["mfma_busy"] = float(f["mfma_busy"])
+        if "l2_hit" in f:
+            out["l2_hit"] = float(f["l2_hit"])
+        return out
     return None
 
 
@@ -80,7 +86,8 @@ def roofline_entry(kernel, flops, bytes_alg, ms_total, launches, matrix_core, wo
     t = ms_total * 1e-3
     t_hbm = bytes_alg / (HBM_PEAK_GBS * 1e9)
     t_fp = flops / (FP64_VECTOR_PEAK_TF * 1e12)
-    traffic = measured_traffic(kernel, workload)
+    counters = measured_counters(kernel, workload)
+    traffic = counters["traffic"] if counters else None
     if t_fp >= t_hbm:
         ach = flops / t / 1e12
         out = {"kernel": kernel, "bound": "mfma" if matrix_core else "alu",
@@ -97,6 +104,11 @@ def roofline_entry(kernel, flops, bytes_alg, ms_total, launches, matrix_core, wo
     out["launches"] = launches
     if traffic is not None:
         out["traffic_over_alg_bytes"] = round(traffic / (bytes_alg / launches), 2)
+    if matrix_core and counters and "mfma_busy" in counters:
+        # measured matrix-core busy fraction beside the algorithmic frac above
+        out["mfma_busy_measured"] = counters["mfma_busy"]
+    if counters and "l2_hit" in counters:
+        out["l2_hit_measured"] = counters["l2_hit"]
     return out
 
 

@@ -169,6 +169,75 @@ def cpu_baseline(w, A, B_host, sample_fraction=1.0 / 32, sweep_entries=1 << 23):
     }
 
 
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_full_runs(names, sylt, torch):
+    """The oracle run in full (not sampled) on the small workloads, phase by
+    phase with a monotonic clock: Schur factors (LAPACK), forward chain,
+    literal sweep, backward chain.  The device's plan + solve of the same
+    inputs is timed beside it."""
+    import numpy as np
+
+    import oracle
+    import sylt_workloads as wl
+
+    out = {}
+    for name in names:
+        w = wl.WORKLOADS[name]
+        n = list(w.n)
+        A = wl.coefficient_matrices(w.n, w.seed)
+        B = wl.rhs(w)
+        t = {}
+        t0 = time.perf_counter()
+        U, T = oracle.factors(A)
+        t["factors_s"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        C = oracle.transform(n, U, B, True)
+        t["forward_s"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        Y, _ = oracle.sweep(n, T, C)
+        t["sweep_s"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        X = oracle.transform(n, U, Y, False)
+        t["backward_s"] = time.perf_counter() - t0
+        total = sum(t.values())
+        A_dev = [torch.from_numpy(a).cuda() for a in A]
+        Bd = torch.from_numpy(B).cuda()
+        Xd = torch.empty_like(Bd)
+
+        def step():
+            plan = sylt.Plan.factor(n, A_dev)
+            sylt.solve(plan, Bd, out=Xd)
+            return plan
+        plans = [step()]  # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record()
+        for _ in range(reps):
+            plans.append(step())
+        e1.record()
+        e1.synchronize()
+        gpu_ms = e0.elapsed_time(e1) / reps
+        for pl in plans:
+            pl.destroy()
+        err = float(np.max(np.abs(Xd.cpu().numpy() - X)) / np.max(np.abs(X)))
+        out[name] = {"n": n, "entries": w.ntot, **{k: round(v, 4) for k, v in t.items()},
+                     "oracle_total_s": round(total, 4),
+                     "oracle_entries_per_s": round(w.ntot / total, 1),
+                     "device_ms": round(gpu_ms, 3), "relmax_device_vs_oracle": err}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -408,7 +477,12 @@ def main():
         log("timing the oracle on a bounded sample")
         Bh = B_host.numpy()
         cpu = cpu_baseline(w, A, Bh)
+        cpu["cpu_model"] = cpu_model()
+        cpu["nproc"] = os.cpu_count()
         log(f"cpu {cpu}")
+        log("the oracle in full on the small workloads")
+        cpu["full_runs"] = oracle_full_runs(["C1", "C2", "C5"], sylt, torch)
+        log(f"oracle full runs {cpu['full_runs']}")
 
     line = {
         "metric": "tensor entries solved/s (FP64 Schur/Bartels-Stewart solve, N=7 n=19)",

@@ -601,6 +601,90 @@ __global__ void __launch_bounds__(kMfmaThreads) transform_mfma_kernel(V *X, cons
     }
 }
 
+// A pass of one mode with extent n > 24 (up to 256) on the matrix cores.  The
+// tile (lb x n x rb entries; fibres of stride lb) sits in LDS.  A wave forms
+// one 16-row block of the real-form product (the layout of the pass above)
+// for 16 fibres at a time: the A fragments come from the matrix in memory
+// (cache resident, a handful of lines per k-step), the B operands from LDS.
+// Results go straight to memory: the whole tile is in LDS before any of it is
+// overwritten, and tiles are disjoint.
+constexpr int kLongThreads = 512;
+constexpr int kLongUnroll = 8;  // k-steps whose operands are loaded together
+
+template <typename V>
+__global__ void __launch_bounds__(kLongThreads) transform_long_mfma_kernel(V *X, const V *Xs,
+                                                                           const V *__restrict__ Mbuf,
+                                                                           PassDesc pa)
+{
+    using R = typename CTraits<V>::R;
+    using MT = MfmaT<R>;
+    const int n = pa.gd[0];
+    const int RB = (n + 7) / 8, KS = (2 * n + 3) / 4;
+    constexpr int WAVES = kLongThreads / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V *tile = reinterpret_cast<V *>(smem_raw);
+    const int total = pa.lb * n * pa.rb;
+    R *tr = reinterpret_cast<R *>(tile);
+    const int zidx = 2 * total;  // a zero operand after the tile
+    if (threadIdx.x == 0) tr[zidx] = R(0);
+    const V *M = Mbuf + pa.moff[0];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kb = lane >> 4, r16 = lane & 15, ap = MT::part_of_row(r16);
+    const int64_t ntiles = pa.ntl * pa.ntr;
+    const TileWalk walk = tile_walk(ntiles);
+    for (int64_t t = walk.t; t < walk.end; t += walk.step) {
+        const TileCoord tc = tile_coord_of(pa, t);
+        __syncthreads();  // every wave is done with the previous tile
+        for (int e = threadIdx.x; e < total; e += kLongThreads) {
+            const int l = e & (pa.lb - 1), rest = e >> pa.lbshift;
+            const int g = rest % n, r = rest / n;
+            V v;
+            v.x = 0;
+            v.y = 0;
+            if (l < tc.lbe && r < tc.rbe) v = Xs[tc.l0 + l + pa.Lin * (g + (int64_t)n * (tc.r0 + r))];
+            tile[e] = v;
+        }
+        __syncthreads();
+        const int nfib = pa.lb * tc.rbe;
+        const int items = ((nfib + 15) >> 4) * RB;
+        for (int it = wave; it < items; it += WAVES) {
+            const int grp = it / RB, rb = it - grp * RB;
+            const int f = 16 * grp + r16;
+            const int fl = f & (pa.lb - 1), fr = f >> pa.lbshift;
+            const bool fok = f < nfib && fl < tc.lbe;
+            const int base = fl + pa.lb * n * fr;
+            const int i = 8 * rb + MT::out_of_row(r16);
+            typename MT::acc acc = {0, 0, 0, 0};
+            for (int kk0 = 0; kk0 < KS; kk0 += kLongUnroll) {
+                R a[kLongUnroll], b[kLongUnroll];
+#pragma unroll
+                for (int u = 0; u < kLongUnroll; ++u) {
+                    const int k = 4 * (kk0 + u) + kb;
+                    const int m = k >> 1;
+                    const bool in = kk0 + u < KS && m < n;
+                    const V c = M[(in && i < n) ? i + (int64_t)n * m : 0];
+                    a[u] = (in && i < n) ? (ap == (k & 1) ? c.x : (ap ? c.y : -c.y)) : R(0);
+                    b[u] = tr[(in && fok) ? 2 * (base + m * pa.lb) + (k & 1) : zidx];
+                }
+#pragma unroll
+                for (int u = 0; u < kLongUnroll; ++u) acc = MT::mma(a[u], b[u], acc);
+            }
+            if (fok) {
+#pragma unroll
+                for (int c2 = 0; c2 < 2; ++c2) {
+                    const int io = 8 * rb + MT::out_of_row(MT::row(lane, 2 * c2));
+                    if (io < n) {
+                        V y;
+                        y.x = acc[2 * c2];
+                        y.y = acc[2 * c2 + 1];
+                        X[tc.l0 + fl + pa.Lin * (io + (int64_t)n * (tc.r0 + fr))] = y;
+                    }
+                }
+            }
+        }
+    }
+}
+
 // extents above 24: ping-pong between two LDS tiles; the work items of a mode
 // are (fibre, chunk of 8 outputs) pairs
 template <typename V>
@@ -1000,6 +1084,20 @@ hipError_t run_transform_pass(const PassDesc &pa, V *X, const V *Xs, const V *Mb
         if (e != hipSuccess) return e;                                                    \
         hipLaunchKernelGGL(KER, dim3((unsigned)tiles), dim3(kThreads), lds, s, X, Xs, Mbuf, pa); \
     } while (0)
+    if (generic && pa.ng == 1) {
+        // one long mode: the matrix-core pass above
+        const size_t ldsl = pa.lds_bytes(sizeof(V)) + 32;
+        auto ker = transform_long_mfma_kernel<V>;
+        e = allow_lds(ker, ldsl);
+        if (e != hipSuccess) return e;
+        int occ = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, ker, kLongThreads, ldsl) != hipSuccess ||
+            occ < 1)
+            occ = 1;
+        const int64_t grid = std::min<int64_t>(tiles, (int64_t)device_cus() * occ);
+        hipLaunchKernelGGL(ker, dim3((unsigned)grid), dim3(kLongThreads), ldsl, s, X, Xs, Mbuf, pa);
+        return hipGetLastError();
+    }
     const bool pipe = !generic && pa.lb * pa.G * pa.rb <= kPipeRegs * kPipeThreads &&
                       (pa.uniform_n == 2 || pa.uniform_n == 4 || pa.uniform_n == 8 ||
                        pa.uniform_n == 16 || pa.uniform_n == 19);

@@ -26,13 +26,14 @@ struct SchurJobs {
     int64_t off[kMaxModes];
 };
 
-// 1/sqrt(x) for a normal positive x: the hardware estimate refined by three
-// Newton steps y <- y + y (1 - x y^2) / 2 (quadratic convergence to rounding)
+// 1/sqrt(x) for a normal positive x: the hardware estimate refined by two
+// Newton steps y <- y + y (1 - x y^2) / 2 (quadratic convergence: each step
+// doubles the correct bits of the estimate)
 __device__ __forceinline__ double rsqrt_nr(double x)
 {
     double y = __builtin_amdgcn_rsq(x);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < 2; ++i) {
         const double e = fma(-(x * y), y, 1.0);
         y = fma(0.5 * y, e, y);
     }
@@ -47,6 +48,23 @@ template <bool FAST>
 __device__ __forceinline__ void givens(double2 a, double2 b, double &c, double2 &s)
 {
     // [c s; -conj(s) c] [a; b] = [r; 0] with real c and c^2 + |s|^2 = 1
+    const double aa = a.x * a.x + a.y * a.y, bb = b.x * b.x + b.y * b.y;
+    // fast form, for |a|^2 and |a|^2 + |b|^2 in [2^-500, 2^500] (which
+    // excludes a = 0): w = 1 / (|a| rho) from one reciprocal square root of
+    // their product, c = |a|^2 w and s = a conj(b) w; this sits on the
+    // critical path of every QR step
+    if (FAST && aa > 0x1p-500 && aa < 0x1p500 && bb < 0x1p500) {
+        const double w = rsqrt_nr(aa * (aa + bb));
+        c = aa * w;
+        s = cscale(cmul(a, cconj(b)), w);
+        // one first-order step towards c^2 + |s|^2 = 1: the products above
+        // carry a few roundings each, and a rotation that is not unitary to
+        // rounding lets U drift from unitarity over many QR sweeps
+        const double g = fma(-0.5, fma(c, c, fma(s.x, s.x, s.y * s.y)), 1.5);
+        c *= g;
+        s = cscale(s, g);
+        return;
+    }
     if (b.x == 0.0 && b.y == 0.0) {
         c = 1.0;
         s = cd(0.0, 0.0);
@@ -56,23 +74,6 @@ __device__ __forceinline__ void givens(double2 a, double2 b, double &c, double2 
         const double absb = cabs2(b);
         c = 0.0;
         s = cd(b.x / absb, -b.y / absb);
-        return;
-    }
-    // moduli in [2^-480, 2^480]: the squares are normal and finite, so
-    // c = |a| / rho = |a|^2 / (|a| rho) and s = a conj(b) / (|a| rho) come from
-    // two independent reciprocal square roots of the sums of squares (a short
-    // dependence chain: this sits on the critical path of a QR sweep)
-    const double aa = a.x * a.x + a.y * a.y, bb = b.x * b.x + b.y * b.y;
-    if (FAST && aa > 0x1p-960 && aa < 0x1p960 && bb > 0x1p-960 && bb < 0x1p960) {
-        const double w = rsqrt_nr(aa) * rsqrt_nr(aa + bb);
-        c = aa * w;
-        s = cscale(cmul(a, cconj(b)), w);
-        // one first-order step towards c^2 + |s|^2 = 1: the products above
-        // carry a few roundings each, and a rotation that is not unitary to
-        // rounding lets U drift from unitarity over many QR sweeps
-        const double g = fma(-0.5, fma(c, c, fma(s.x, s.x, s.y * s.y)), 1.5);
-        c *= g;
-        s = cscale(s, g);
         return;
     }
     const double absa = cabs2(a), absb = cabs2(b);
@@ -96,8 +97,10 @@ __device__ __forceinline__ void givens(double2 a, double2 b, double &c, double2 
 // Rows (columns) are loaded in groups of kQrGroup, one group ahead: with
 // stores in flight, a wait on a load waits for every memory operation before
 // it, so the groups leave one wait per kQrGroup steps.  Loads are unconditional
-// from clamped addresses and masked afterwards (a load under a lane branch is
-// waited for at the join).
+// from clamped addresses and used as loaded: a value outside the window is
+// never used (the step's own lane test excludes it), while masking it (or
+// subtracting the shift) right after the load would overwrite the load's
+// register and so wait for the load at once, every step.
 constexpr int kQrGroup = 8;
 
 __device__ __forceinline__ int qr_block(double2 *H, double2 *Q, int n, int tid, int maxit,
@@ -141,16 +144,20 @@ __device__ __forceinline__ int qr_block(double2 *H, double2 *Q, int n, int tid, 
         }
         // left rotations: this lane's entry of row r of H_w - mu I
         const int col = tid;
+        // loads from clamped addresses, used as loaded: every lane whose
+        // value lies outside the window is masked where it is used, and
+        // masking or shifting a value right after its load would make the
+        // load wait at once (an overwrite of a load's register waits for it)
         auto ld_row = [&](int r) __attribute__((always_inline)) {
-            double2 v = HH(min(r, n - 1), min(col, n - 1));
-            if (col == r) v = csub(v, mu);
-            return (col < n && r <= hi) ? v : cd(0.0, 0.0);
+            return HH(min(r, n - 1), min(col, n - 1));
         };
         double2 cur = ld_row(lo), ra[G], rb[G];
+        if (col == lo) cur = csub(cur, mu);
 #pragma unroll
         for (int i = 0; i < G; ++i) ra[i] = ld_row(lo + 1 + i);
         auto lstep = [&](int k, double2 R) __attribute__((always_inline)) {
             if (k >= hi) return;
+            if (col == k + 1) R = csub(R, mu);  // row k+1 of H_w - mu I
             double2 *slot = bc + 2 * (k & 1);
             if (col == k) {
                 slot[0] = cur;
@@ -188,8 +195,7 @@ __device__ __forceinline__ int qr_block(double2 *H, double2 *Q, int n, int tid, 
         const int r = tid;
         auto right = [&](double2 *M, bool isH) __attribute__((always_inline)) {
             auto ld_col = [&](int j) __attribute__((always_inline)) {
-                const double2 v = M[min(r, n - 1) + n * min(j, n - 1)];
-                return (j <= hi && r < n && (!isH || r <= j)) ? v : cd(0.0, 0.0);
+                return M[min(r, n - 1) + n * min(j, n - 1)];
             };
             const double2 c0 = M[min(r, n - 1) + n * lo];
             double2 cc = (r < n && (!isH || r <= lo + 1)) ? c0 : cd(0.0, 0.0);

@@ -887,7 +887,14 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
     const int64_t ntiles = pa.ntl * pa.ntr;
     const TileWalk walk = tile_walk(ntiles);
     int64_t t = walk.t;
-    if (t >= walk.end) return;
+    // the norms' partial sums: each lane adds its entries of all the
+    // workgroup's tiles (in the fixed order of the walk), and the workgroup
+    // reduces them once at the end, into slot blockIdx.x
+    double sb_all = 0.0, sr_all = 0.0;
+    if (t >= walk.end) {
+        residual_reduce(sb_all, sr_all, first, last, part_b, part_r, blockIdx.x, smem_raw);
+        return;
+    }
     const double2 *src = first ? B : R;
     double pre_re[kResidualRegs], pre_im[kResidualRegs], src_re[kResidualRegs], src_im[kResidualRegs];
     auto gaddr = [&](const TileCoord &c, int e, bool &ok) -> int64_t {
@@ -1012,12 +1019,14 @@ __global__ void __launch_bounds__(kMfmaThreads) residual_mfma_kernel(
                 if (!last || !R32) R[gi] = v;
             }
         }
-        residual_reduce(sb, sr, first, last, part_b, part_r, t, smem_raw);
+        sb_all += sb;
+        sr_all += sr;
         if (tn >= walk.end) break;
         __syncthreads();
         t = tn;
         tc = tcn;
     }
+    residual_reduce(sb_all, sr_all, first, last, part_b, part_r, blockIdx.x, smem_raw);
 }
 
 // one workgroup of kReduceThreads lanes, fixed order: lane l sums entries
@@ -1238,6 +1247,7 @@ hipError_t launch_residual_with(const sylt_plan_s &p, const double2 *Mbuf, const
         const int first = i == 0, last = i == P - 1;
         hipError_t e;
         if (p.residual_mfma) {
+            int64_t mgrid = 0;  // workgroups of the pass: one partial sum each
 #define SYLT_MRLAUNCH(NNV)                                                                        \
     do {                                                                                          \
         const size_t mlds = residual_mfma_lds(pa);                                                \
@@ -1249,6 +1259,7 @@ hipError_t launch_residual_with(const sylt_plan_s &p, const double2 *Mbuf, const
             occ < 1)                                                                              \
             occ = 1;                                                                              \
         const int64_t grid = std::min<int64_t>(tiles, (int64_t)device_cus() * occ);              \
+        mgrid = grid;                                                                             \
         hipLaunchKernelGGL(residual_mfma_kernel<NNV>, dim3((unsigned)grid), dim3(kMfmaThreads),   \
                            mlds, s, B, X, R64, last ? R32 : nullptr, Mbuf, pa, sing, first, last, \
                            part_b, part_r, r32_scale);                                            \
@@ -1263,10 +1274,10 @@ hipError_t launch_residual_with(const sylt_plan_s &p, const double2 *Mbuf, const
             e = hipGetLastError();
             if (e != hipSuccess) return e;
             if (first && norms2_dev)
-                hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(kReduceThreads), 0, s, part_b, tiles,
+                hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(kReduceThreads), 0, s, part_b, mgrid,
                                    norms2_dev + 1);
             if (last && norms2_dev)
-                hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(kReduceThreads), 0, s, part_r, tiles,
+                hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(kReduceThreads), 0, s, part_r, mgrid,
                                    norms2_dev + 0);
             continue;
         }

@@ -122,24 +122,38 @@ __device__ __forceinline__ void pull_mode(const V *__restrict__ X, const double2
 #pragma unroll
         for (int r = 0; r < BJ; ++r) acc[r] = make_double2(0.0, 0.0);
         for (int kb = k0; kb < k1; kb += NP) {
-            double2 y[NP];
+            // the loads of a chunk are issued together and waited for at the
+            // first use.  Stored as complex64, the entries stay in that type
+            // until they are used: a conversion next to its load would wait
+            // for that load alone, one memory latency per entry.
+            using L = std::conditional_t<std::is_same<V, double2>::value, double2, V>;
+            L y[NP];
 #pragma unroll
-            for (int u = 0; u < NP; ++u)
-                y[u] = kb + u < k1 ? to_d2<V>(src[(int64_t)(kb + u) * sj]) : make_double2(0.0, 0.0);
+            for (int u = 0; u < NP; ++u) {
+                if constexpr (std::is_same<V, double2>::value)
+                    y[u] = kb + u < k1 ? src[(int64_t)(kb + u) * sj] : make_double2(0.0, 0.0);
+                else if (kb + u < k1)
+                    y[u] = src[(int64_t)(kb + u) * sj];
+            }
 #pragma unroll
             for (int u = 0; u < NP; ++u) {
                 const int k = kb + u;
                 if (k >= k1) break;  // uniform
+                const double2 yu = to_d2<V>(y[u]);
 #pragma unroll
                 for (int r = 0; r < BJ; ++r) {
                     if (r < e) {
                         if (ADJ)
-                            acc[r] = cmac_conj(acc[r], Tj[k + (int64_t)d * (o + r)], y[u]);
+                            acc[r] = cmac_conj(acc[r], Tj[k + (int64_t)d * (o + r)], yu);
                         else
-                            acc[r] = cmac(acc[r], Tj[(o + r) + (int64_t)d * k], y[u]);
+                            acc[r] = cmac(acc[r], Tj[(o + r) + (int64_t)d * k], yu);
                     }
                 }
             }
+            // complex64: every load of the chunk has been used.  Without this
+            // wait (vmcnt(0), the other counters left alone) the compiler
+            // waits before reusing a load's register in the next chunk.
+            if constexpr (!std::is_same<V, double2>::value) __builtin_amdgcn_s_waitcnt(0x0f70);
         }
 #pragma unroll
         for (int r = 0; r < BJ; ++r)

@@ -98,12 +98,89 @@ __device__ __forceinline__ bool entry_ok(uint64_t c, const SweepDesc &sd, const 
     return true;
 }
 
+// Pull of one mode for a short k range (at most NP2 terms): every lane takes
+// two cross-section positions per round, c and c + blockDim.x, so a round
+// keeps as many loads in flight as a full round of the one-position form and
+// the mode needs half as many rounds (each round costs about one memory
+// latency).  A position outside a ragged tile borrows the other position's
+// addresses and its result is dropped.
+template <typename V, bool ADJ, int MC, int BJ, int NP2>
+__device__ __forceinline__ void pull_mode_pairs(const V *__restrict__ X,
+                                                const double2 *__restrict__ Tj,
+                                                const int *__restrict__ cj,
+                                                const int64_t *__restrict__ goff,
+                                                const uint64_t *__restrict__ code,
+                                                const SweepDesc &sd, const TileState &ts,
+                                                double2 *tile, int o, int e, int d, int k0, int k1,
+                                                int lsj, int64_t sj, int cs)
+{
+    const int step = blockDim.x;
+    for (int c = threadIdx.x; c < cs; c += 2 * step) {
+        const int ta = cj[c];
+        const bool inb = c + step < cs;
+        const int tb = inb ? cj[c + step] : ta;
+        const bool va = !ts.ragged || entry_ok<MC>(code[ta], sd, ts);
+        const bool vb = inb && (!ts.ragged || entry_ok<MC>(code[tb], sd, ts));
+        if (!va && !vb) continue;
+        const int64_t ga = goff[ta], gb = goff[tb];
+        const V *sa = X + ts.base + (va ? ga : gb) - (int64_t)o * sj;
+        const V *sb = X + ts.base + (vb ? gb : ga) - (int64_t)o * sj;
+        double2 acca[BJ], accb[BJ];
+#pragma unroll
+        for (int r = 0; r < BJ; ++r) acca[r] = accb[r] = make_double2(0.0, 0.0);
+        using L = std::conditional_t<std::is_same<V, double2>::value, double2, V>;
+        L ya[NP2], yb[NP2];
+#pragma unroll
+        for (int u = 0; u < NP2; ++u) {
+            if constexpr (std::is_same<V, double2>::value) {
+                ya[u] = k0 + u < k1 ? sa[(int64_t)(k0 + u) * sj] : make_double2(0.0, 0.0);
+                yb[u] = k0 + u < k1 ? sb[(int64_t)(k0 + u) * sj] : make_double2(0.0, 0.0);
+            } else if (k0 + u < k1) {
+                ya[u] = sa[(int64_t)(k0 + u) * sj];
+                yb[u] = sb[(int64_t)(k0 + u) * sj];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NP2; ++u) {
+            const int k = k0 + u;
+            if (k >= k1) break;  // uniform
+            const double2 ua = to_d2<V>(ya[u]), ub = to_d2<V>(yb[u]);
+#pragma unroll
+            for (int r = 0; r < BJ; ++r) {
+                if (r < e) {
+                    if (ADJ) {
+                        const double2 t = Tj[k + (int64_t)d * (o + r)];
+                        acca[r] = cmac_conj(acca[r], t, ua);
+                        accb[r] = cmac_conj(accb[r], t, ub);
+                    } else {
+                        const double2 t = Tj[(o + r) + (int64_t)d * k];
+                        acca[r] = cmac(acca[r], t, ua);
+                        accb[r] = cmac(accb[r], t, ub);
+                    }
+                }
+            }
+        }
+        if constexpr (!std::is_same<V, double2>::value) __builtin_amdgcn_s_waitcnt(0x0f70);
+        if (va) {
+#pragma unroll
+            for (int r = 0; r < BJ; ++r)
+                if (r < e) tile[ta + r * lsj] = csub(tile[ta + r * lsj], acca[r]);
+        }
+        if (vb) {
+#pragma unroll
+            for (int r = 0; r < BJ; ++r)
+                if (r < e) tile[tb + r * lsj] = csub(tile[tb + r * lsj], accb[r]);
+        }
+    }
+}
+
 // Pull of one mode: for every cross-section position of the tile (one per
 // lane and round), the rows of the block receive
 //   sum over k outside the block of T_j[row, k] * Y[..., k, ...]
 // (k above the block for the upper sweep, below it for the adjoint).  BJ is
-// the block size, NP the loads a lane keeps in flight.
-template <typename V, bool ADJ, int MC, int BJ, int NP>
+// the block size, NP the loads a lane keeps in flight; PAIRS lets a short k
+// range take the two-position form.
+template <typename V, bool ADJ, int MC, int BJ, int NP, bool PAIRS>
 __device__ __forceinline__ void pull_mode(const V *__restrict__ X, const double2 *__restrict__ Tj,
                                           const int *__restrict__ cj,
                                           const int64_t *__restrict__ goff,
@@ -111,6 +188,13 @@ __device__ __forceinline__ void pull_mode(const V *__restrict__ X, const double2
                                           const TileState &ts, double2 *tile, int o, int e, int d,
                                           int k0, int k1, int lsj, int64_t sj, int cs)
 {
+    if constexpr (PAIRS && BJ <= 3) {
+        if (2 * (k1 - k0) <= NP) {  // uniform
+            pull_mode_pairs<V, ADJ, MC, BJ, NP / 2>(X, Tj, cj, goff, code, sd, ts, tile, o, e, d,
+                                                    k0, k1, lsj, sj, cs);
+            return;
+        }
+    }
     for (int c = threadIdx.x; c < cs; c += blockDim.x) {
         // cross-section position c -> local entry t0 (loc_j = 0), from the
         // plan's table; its global offset and, in a ragged tile, whether it
@@ -269,7 +353,7 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
         switch (b) {
 #define SYLT_PULL(BJ, NP)                                                                         \
     case BJ:                                                                                      \
-        pull_mode<V, ADJ, MC, BJ, NP>(X, Tj, cj, goff, code, sd, ts, tile, o, e, d, k0, k1, lsj, sj, \
+        pull_mode<V, ADJ, MC, BJ, NP, PEN>(X, Tj, cj, goff, code, sd, ts, tile, o, e, d, k0, k1, lsj, sj, \
                                       cs);                                                        \
         break;
             SYLT_PULL(1, 16) SYLT_PULL(2, 16) SYLT_PULL(3, 16) SYLT_PULL(4, 12)

@@ -432,9 +432,13 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
         const int e0 = __builtin_amdgcn_readfirstlane(ts.e[0]);
         const int64_t r0 = __builtin_amdgcn_readfirstlane(ts.o[0]);
         const int64_t d0 = sd.d[0];
-        // column K of T_0 (adjoint) or row K of T_0 (= column K of T_0^T): the
-        // mode-0 coefficients of entry K are contiguous there
-        const double2 *Tcol = (ADJ ? Tbuf : Ttbuf) + sd.moff[0] + r0;
+        // column K of T_0 (row K, i.e. column K of T_0^T, for the adjoint):
+        // the coefficients with which entry K enters the entries solved after
+        // it are contiguous there
+        const double2 *Tcol = (ADJ ? Ttbuf : Tbuf) + sd.moff[0] + r0;
+        // y[K]: minus the mode-0 sum of entry K over the entries already
+        // solved, added to as each of them is solved (right-looking), so an
+        // entry's own solve does not wait on a chain of multiply-adds
         double2 y[kPen];
 #pragma unroll
         for (int i = 0; i < kPen; ++i) y[i] = make_double2(0.0, 0.0);
@@ -444,20 +448,7 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
             constexpr int K = decltype(kc)::value;
             const int t = t0 + K;
             const double2 *cf = Tcol + d0 * (r0 + K);
-            double2 num = tile[t];
-            if (ADJ) {
-#pragma unroll
-                for (int kk = 0; kk < K; ++kk) num = cmsub_conj(num, cf[kk], y[kk]);
-            } else {
-                // past the block end y is zero; the coefficient index stays in it
-#pragma unroll
-                for (int kb = (K + 1) & ~(kChunk0 - 1); kb < kPen; kb += kChunk0) {
-                    if (kb >= e0) break;  // uniform
-#pragma unroll
-                    for (int kk = kb; kk < kb + kChunk0; ++kk)
-                        if (kk > K) num = cmsub(num, cf[min(kk, e0 - 1)], y[kk]);
-                }
-            }
+            double2 num = cadd(tile[t], y[K]);
             double2 yk = make_double2(0.0, 0.0);
             if (act) {
                 const double2 lam0 = cf[K];
@@ -485,7 +476,22 @@ __global__ void __launch_bounds__(kThreads) sweep_tile_kernel(
                 yk = cdiv_scaled(num, den);
                 tile[t] = yk;
             }
-            y[K] = yk;
+            // pass y_K on to the entries still to be solved (an inactive lane
+            // passes zero)
+            if (ADJ) {
+                // entries past the block end are never solved; the coefficient
+                // index stays in the block
+#pragma unroll
+                for (int kb = (K + 1) & ~(kChunk0 - 1); kb < kPen; kb += kChunk0) {
+                    if (kb >= e0) break;  // uniform
+#pragma unroll
+                    for (int kk = kb; kk < kb + kChunk0; ++kk)
+                        if (kk > K) y[kk] = cmsub_conj(y[kk], cf[min(kk, e0 - 1)], yk);
+                }
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk) y[kk] = cmsub(y[kk], cf[kk], yk);
+            }
         };
         // A wave is active at the e0 local levels g .. g + e0 - 1, one entry
         // each; before and after them it only takes part in the barriers, so

@@ -189,10 +189,23 @@ __device__ __forceinline__ void pull_mode(const V *__restrict__ X, const double2
                                           int k0, int k1, int lsj, int64_t sj, int cs)
 {
     if constexpr (PAIRS && BJ <= 3) {
-        if (2 * (k1 - k0) <= NP) {  // uniform
-            pull_mode_pairs<V, ADJ, MC, BJ, NP / 2>(X, Tj, cj, goff, code, sd, ts, tile, o, e, d,
+        if constexpr (std::is_same<V, double2>::value) {
+            if (2 * (k1 - k0) <= NP) {  // uniform
+                pull_mode_pairs<V, ADJ, MC, BJ, NP / 2>(X, Tj, cj, goff, code, sd, ts, tile, o, e,
+                                                        d, k0, k1, lsj, sj, cs);
+                return;
+            }
+        } else {
+            if (2 * (k1 - k0) <= NP) {  // uniform
+                pull_mode_pairs<V, ADJ, MC, BJ, NP / 2>(X, Tj, cj, goff, code, sd, ts, tile, o, e,
+                                                        d, k0, k1, lsj, sj, cs);
+                return;
+            }
+            if (k1 - k0 <= NP) {  // uniform
+                pull_mode_pairs<V, ADJ, MC, BJ, NP>(X, Tj, cj, goff, code, sd, ts, tile, o, e, d,
                                                     k0, k1, lsj, sj, cs);
-            return;
+                return;
+            }
         }
     }
     for (int c = threadIdx.x; c < cs; c += blockDim.x) {
